@@ -1,0 +1,211 @@
+"""Random graph generators (stochastic block model, Chung-Lu) and CSR assembly.
+
+Every generator is seeded and vectorised with NumPy so that graphs with
+tens of millions of edges build in seconds.  Graphs are undirected and
+simple: the CSR holds both (i, j) and (j, i), no duplicates and no
+self-loops (self-loops, when a workload wants them, are added by the
+design-matrix operator, not here).  Column indices are sorted inside each
+row.  Edge weights are not drawn: every stored entry of A is 1.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Graph:
+    """Pattern of an undirected graph in CSR form.
+
+    indptr  : int64 array of n+1 row offsets
+    indices : int32 array of nnz column indices, sorted inside each row
+    blocks  : optional int32 array of n block labels (SBM graphs)
+    """
+
+    n: int
+    indptr: np.ndarray
+    indices: np.ndarray
+    blocks: np.ndarray | None = None
+
+    @property
+    def nnz(self) -> int:
+        return int(self.indptr[-1])
+
+    def row_lengths(self) -> np.ndarray:
+        return np.diff(self.indptr)
+
+
+def edges_to_csr(n: int, src: np.ndarray, dst: np.ndarray, blocks=None) -> Graph:
+    """Symmetric CSR from an undirected edge list (i != j).
+
+    Duplicate pairs (in either orientation) are merged; self-pairs are
+    dropped.
+    """
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    keep = src != dst
+    src, dst = src[keep], dst[keep]
+    lo = np.minimum(src, dst)
+    hi = np.maximum(src, dst)
+    code = np.unique(lo * n + hi)
+    lo = code // n
+    hi = code % n
+    rows = np.concatenate([lo, hi])
+    cols = np.concatenate([hi, lo])
+    order = np.argsort(rows * n + cols, kind="stable")
+    rows = rows[order]
+    cols = cols[order]
+    counts = np.bincount(rows, minlength=n)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=indptr[1:])
+    return Graph(n=n, indptr=indptr, indices=cols.astype(np.int32), blocks=blocks)
+
+
+def _block_sizes(n: int, num_blocks: int) -> np.ndarray:
+    # When num_blocks does not divide n the first n mod B blocks get one extra node.
+    base = n // num_blocks
+    sizes = np.full(num_blocks, base, dtype=np.int64)
+    sizes[: n - base * num_blocks] += 1
+    return sizes
+
+
+def sbm_graph(n: int, num_blocks: int, p_in: float, p_out: float, seed: int) -> Graph:
+    """Stochastic block model with Bernoulli(p_in / p_out) edges over pairs i < j.
+
+    Blocks are contiguous node ranges.  For n <= 6000 every pair is drawn
+    explicitly.  For larger n each block pair draws its edge count from
+    the binomial law and then that many distinct uniform pairs, which is
+    the same distribution.
+    """
+    rng = np.random.default_rng(seed)
+    sizes = _block_sizes(n, num_blocks)
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    labels = np.repeat(np.arange(num_blocks, dtype=np.int32), sizes)
+    if n <= 6000:
+        iu, ju = np.triu_indices(n, k=1)
+        same = labels[iu] == labels[ju]
+        prob = np.where(same, p_in, p_out)
+        hit = rng.random(iu.shape[0]) < prob
+        return edges_to_csr(n, iu[hit], ju[hit], blocks=labels)
+    srcs, dsts = [], []
+    for a in range(num_blocks):
+        for b in range(a, num_blocks):
+            na, nb = int(sizes[a]), int(sizes[b])
+            pairs = na * (na - 1) // 2 if a == b else na * nb
+            p = p_in if a == b else p_out
+            m = int(rng.binomial(pairs, p)) if pairs > 0 else 0
+            if m == 0:
+                continue
+            got_s = np.empty(0, np.int64)
+            got_d = np.empty(0, np.int64)
+            need = m
+            while need > 0:
+                draw = int(need * 1.05) + 16
+                if a == b:
+                    s = rng.integers(0, na, draw)
+                    d = rng.integers(0, na, draw)
+                    ok = s != d
+                    s, d = np.minimum(s[ok], d[ok]), np.maximum(s[ok], d[ok])
+                else:
+                    s = rng.integers(0, na, draw)
+                    d = rng.integers(0, nb, draw)
+                s = np.concatenate([got_s, s + starts[a]])
+                d = np.concatenate([got_d, d + starts[b]])
+                code, first = np.unique(s * n + d, return_index=True)
+                first = np.sort(first)[:m]
+                got_s, got_d = s[first], d[first]
+                need = m - got_s.shape[0]
+            srcs.append(got_s)
+            dsts.append(got_d)
+    src = np.concatenate(srcs) if srcs else np.empty(0, np.int64)
+    dst = np.concatenate(dsts) if dsts else np.empty(0, np.int64)
+    return edges_to_csr(n, src, dst, blocks=labels)
+
+
+def sbm_graph_by_degree(n: int, num_blocks: int, mean_degree: float, frac_in: float, seed: int) -> Graph:
+    """SBM whose p_in / p_out give an expected degree `mean_degree` with a
+    fraction `frac_in` of each node's edges inside its block."""
+    size = n / num_blocks
+    p_in = mean_degree * frac_in / max(size - 1.0, 1.0)
+    p_out = mean_degree * (1.0 - frac_in) / max(n - size, 1.0)
+    return sbm_graph(n, num_blocks, p_in, p_out, seed)
+
+
+def chung_lu_weights(n: int, beta: float, mean_degree: float) -> np.ndarray:
+    """Expected degrees w_i proportional to (i+1)^(-1/(beta-1)), capped at
+    sqrt(n * mean_degree) and rescaled so that their mean is mean_degree."""
+    gamma = 1.0 / (beta - 1.0)
+    w = np.power(np.arange(1, n + 1, dtype=np.float64), -gamma)
+    cap = np.sqrt(n * mean_degree)
+    w *= mean_degree / w.mean()
+    for _ in range(50):
+        w = np.minimum(w, cap)
+        w *= mean_degree / w.mean()
+        if w.max() <= cap * (1 + 1e-12):
+            break
+    return np.minimum(w, cap)
+
+
+def chung_lu_graph(n: int, beta: float, mean_degree: float, seed: int) -> Graph:
+    """Approximate Chung-Lu power-law graph by endpoint sampling.
+
+    n*mean_degree/2 edges are drawn with both endpoints chosen
+    independently with probability proportional to w; self-pairs and
+    repeated pairs are then removed, so that node i ends with expected
+    degree close to (slightly below, for the largest hubs) w_i.  Nodes
+    are numbered by decreasing weight, so hubs sit at low indices.
+    Isolated nodes are kept.
+    """
+    rng = np.random.default_rng(seed)
+    w = chung_lu_weights(n, beta, mean_degree)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    m = int(round(n * mean_degree / 2.0))
+    chunk = 1 << 22
+    srcs, dsts = [], []
+    for start in range(0, m, chunk):
+        cnt = min(chunk, m - start)
+        s = np.searchsorted(cdf, rng.random(cnt), side="right")
+        d = np.searchsorted(cdf, rng.random(cnt), side="right")
+        srcs.append(np.minimum(s, n - 1))
+        dsts.append(np.minimum(d, n - 1))
+    return edges_to_csr(n, np.concatenate(srcs), np.concatenate(dsts))
+
+
+def cycle_graph(n: int) -> Graph:
+    """Cycle C_n (every node joined to its two ring neighbours), n >= 3."""
+    i = np.arange(n, dtype=np.int64)
+    return edges_to_csr(n, i, (i + 1) % n)
+
+
+def complete_graph(n: int) -> Graph:
+    """Complete graph K_n without self-loops."""
+    iu, ju = np.triu_indices(n, k=1)
+    return edges_to_csr(n, iu, ju)
+
+
+def random_pattern(n_rows: int, n_cols: int, density: float, seed: int, hub_rows: int = 0,
+                   hub_len: int = 0, empty_rows: int = 0):
+    """Random (possibly rectangular, non-symmetric) CSR pattern for kernel tests.
+
+    A few rows can be made dense "hubs" and a few left empty to exercise the
+    long-row and empty-row cases.  Returns (indptr int64, indices int32).
+    """
+    rng = np.random.default_rng(seed)
+    lens = rng.binomial(n_cols, density, size=n_rows).astype(np.int64)
+    if hub_rows:
+        hubs = rng.choice(n_rows, size=min(hub_rows, n_rows), replace=False)
+        lens[hubs] = min(hub_len, n_cols)
+    if empty_rows:
+        empt = rng.choice(n_rows, size=min(empty_rows, n_rows), replace=False)
+        lens[empt] = 0
+    indptr = np.zeros(n_rows + 1, dtype=np.int64)
+    np.cumsum(lens, out=indptr[1:])
+    indices = np.empty(int(indptr[-1]), dtype=np.int32)
+    for r in range(n_rows):
+        ln = int(lens[r])
+        if ln:
+            indices[indptr[r]:indptr[r + 1]] = np.sort(rng.choice(n_cols, size=ln, replace=False))
+    return indptr, indices

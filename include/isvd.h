@@ -1,0 +1,265 @@
+/*
+ * isvd.h -- C ABI of the MI355X implicit randomized truncated SVD library.
+ *
+ * The library computes the rank-k SVD of a design matrix M that is never
+ * formed (Algorithm 1 of Abu-El-Haija et al., "Implicit SVD for Graph
+ * Representation Learning", NeurIPS 2021).  M is known only through
+ * products M*G and M^T*G with tall-skinny dense blocks G (Section 4; the
+ * appendix on symbolic representation: a matrix is usable once it offers
+ * its shape, a product with an explicit block, and its transpose).
+ *
+ * Two design-matrix forms are built in:
+ *   ISVD_FORM_NE       M = sum_{j=1..K} c_j T^j - lambda (1 1^T - A),  n x n
+ *                      with T = D^-1 A (Section 2) and explicit weights c_j
+ *                      (Eq. 2 takes an expectation over walk lengths; Fig. 1
+ *                      builds the same matrix symbolically).
+ *   ISVD_FORM_FEATPROP M = [X, Ahat X, Ahat^2 X, ..., Ahat^L X],  n x d(L+1)
+ *                      with Ahat = (D+I)^-1/2 (A+I) (D+I)^-1/2 (Section 2, Eq. 6).
+ *
+ * Conventions (all entry points):
+ *  - Every array argument is DEVICE memory unless its comment says "host".
+ *    The caller owns all memory it passes.  An operator borrows the graph
+ *    arrays and X for its whole lifetime (they must stay valid and
+ *    unchanged); it owns what it derives (degrees, scales, self-loop CSR,
+ *    workspace).
+ *  - Dense blocks are row-major with a leading dimension (elements between
+ *    consecutive rows) >= their number of columns.  Their element type is
+ *    the operator's precision: double (ISVD_FP64), float (ISVD_FP32) or
+ *    bfloat16 bit patterns, uint16_t (ISVD_BF16).
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *  - Every function returns an isvd_status; on failure the outputs are
+ *    undefined, the operator stays valid and isvd_last_error() describes
+ *    the failure.  No C++ exception crosses this boundary.
+ *  - Operators are not thread-safe: calls on one operator must not overlap.
+ */
+#ifndef ISVD_H
+#define ISVD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ISVD_OK = 0,
+  ISVD_E_INVALID = 1,       /* bad argument: shape mismatch, null pointer, k+p > min(r,c) ... */
+  ISVD_E_OOM = 2,           /* device allocation failed */
+  ISVD_E_HIP = 3,           /* a HIP runtime call failed */
+  ISVD_E_NOT_SPD = 4,       /* Cholesky breakdown: Gram matrix not positive definite */
+  ISVD_E_NOT_CONVERGED = 5, /* tolerance mode reached max_iter before the tolerance */
+  ISVD_E_UNSUPPORTED = 6    /* valid request this build does not implement */
+} isvd_status;
+
+typedef enum {
+  ISVD_FP64 = 0,  /* blocks and products in double */
+  ISVD_FP32 = 1,  /* blocks in float, FP32 accumulation */
+  ISVD_BF16 = 2   /* blocks stored as bfloat16, FP32 accumulation */
+} isvd_precision;
+
+typedef enum {
+  ISVD_FORM_NE = 0,
+  ISVD_FORM_FEATPROP = 1
+} isvd_form;
+
+/* Sparse adjacency A (n x n) in CSR form, device memory, borrowed.
+ * indptr has n+1 non-decreasing entries with indptr[0] = 0; indices holds
+ * column ids in [0, n).  values == NULL means every stored entry is 1.
+ * A directed graph (symmetric == 0) also passes the CSR of A^T in t_*
+ * (t_values NULL iff values NULL).  add_self_loops replaces A by A + I
+ * everywhere (degrees, T and the lambda term) for the NE form; the
+ * feature-propagation form always adds I inside Ahat. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* indptr;
+  const int32_t* indices;
+  const float* values;
+  int symmetric;
+  const int64_t* t_indptr;
+  const int32_t* t_indices;
+  const float* t_values;
+  int add_self_loops;
+} isvd_graph;
+
+/* Design-matrix description.  coeffs is a HOST array of K doubles
+ * (c_1..c_K), copied at creation.  X is a device n x d block in the
+ * operator's precision (row-major, leading dimension ldx), borrowed. */
+typedef struct {
+  isvd_form form;
+  int K;
+  const double* coeffs;
+  double lambda;
+  const void* X;
+  int64_t d;
+  int64_t ldx;
+  int L;
+} isvd_design;
+
+typedef struct isvd_operator isvd_operator;
+
+const char* isvd_status_string(isvd_status s);
+/* Message of the last failure on the calling thread ("" if none). */
+const char* isvd_last_error(void);
+/* Library version string (static). */
+const char* isvd_version(void);
+
+/* Build an operator for M from a graph and a design-matrix description
+ * (Section 4: the implicit matrix).  Computes degrees D = diag(A 1), D^-1
+ * (0 for zero-degree nodes, as in T's definition), (D+I)^-1/2 for the
+ * feature form, and a CSR of A + I when self-loops are requested.  Work is
+ * queued on `stream` and finished before return.
+ * Errors: ISVD_E_INVALID (null pointers, n <= 0, K < 1, d < 1, L < 0,
+ * non-symmetric graph without t_* arrays), ISVD_E_OOM, ISVD_E_HIP. */
+isvd_status isvd_create_operator(const isvd_graph* graph, const isvd_design* design,
+                                 isvd_precision precision, void* stream, isvd_operator** out);
+
+/* Release the operator and everything it owns.  NULL is ignored. */
+void isvd_destroy_operator(isvd_operator* op);
+
+/* (rows, cols) of M: (n, n) for NE, (n, d(L+1)) for FEATPROP (host outputs). */
+isvd_status isvd_operator_shape(const isvd_operator* op, int64_t* rows, int64_t* cols);
+
+/* out = M * Y (transpose == 0; Y is cols x ncols, out is rows x ncols) or
+ * out = M^T * Y (transpose != 0; Y is rows x ncols, out is cols x ncols)
+ * -- the `dot` of the appendix's symbolic-matrix interface and of its
+ * transpose `T`.  Y and out must not overlap.  Enqueued on `stream`
+ * only; returns without synchronising.
+ * Errors: ISVD_E_INVALID (null pointers, ncols < 1 or > 1024, ld < ncols). */
+isvd_status isvd_matmul_block(isvd_operator* op, int transpose, const void* Y, int64_t ldy,
+                              int64_t ncols, void* out, int64_t ldo, void* stream);
+
+/* Parameters of isvd_truncated_svd.  l = k + p columns are carried
+ * (Algorithm 1 carries 2k; here the width is the caller's).
+ *  q         : power iterations in fixed mode (tol <= 0), as Algorithm 1's
+ *              `iterations`.
+ *  tol       : > 0 selects tolerance mode: iterate until the largest
+ *              per-triplet relative residual
+ *                rho = max_i sqrt(|M v_i - s_i u_i|^2 + |M^T u_i - s_i v_i|^2) / s_i
+ *              is <= tol, or max_iter iterations.
+ *  check_every : tolerance mode checks rho every this many iterations (>= 1).
+ *  seed      : Philox seed for a device-drawn Gaussian start block when omega is NULL.
+ *  omega     : optional device c x l start block (operator precision, leading
+ *              dimension ld_omega), used verbatim.
+ *  fp32_switch_tol : BF16 operators only; when > 0 the iteration continues
+ *              in FP32 once rho <= fp32_switch_tol (BF16 alone cannot reach
+ *              small residuals).  U and V are then float. */
+typedef struct {
+  int k;
+  int p;
+  int q;
+  double tol;
+  int max_iter;
+  int check_every;
+  uint64_t seed;
+  const void* omega;
+  int64_t ld_omega;
+  double fp32_switch_tol;
+} isvd_svd_params;
+
+typedef struct {
+  int iterations;        /* power iterations of the returned result (Algorithm 1's `iterations`) */
+  int applies;           /* products with M or M^T performed */
+  int bf16_iterations;   /* of those iterations, how many ran with BF16 blocks */
+  int residual_checks;
+  int used_fallback;     /* 1 if a Cholesky breakdown was repaired by a shifted re-factorisation */
+  double residual;       /* rho of the returned triplets (tolerance mode), else -1 */
+  double seconds;        /* wall time of the call */
+} isvd_svd_info;
+
+/* Rank-k truncated SVD of M (Algorithm 1, with CholeskyQR2 as the
+ * orthonormaliser in place of Algorithm 2's single Cholesky pass):
+ * U (rows x k, leading dimension ldu), S (k doubles, descending), V (cols x k,
+ * leading dimension ldv).  U and V are in the operator's precision, float for
+ * BF16 operators.  Returns after the stream is synchronised.
+ * Errors: ISVD_E_INVALID (k < 1, p < 0, k+p > min(rows, cols), q < 0,
+ * tolerance mode with max_iter < 1), ISVD_E_NOT_SPD (breakdown that the
+ * shifted retry could not repair), ISVD_E_NOT_CONVERGED (outputs then hold
+ * the last iterate), ISVD_E_OOM, ISVD_E_HIP. */
+isvd_status isvd_truncated_svd(isvd_operator* op, const isvd_svd_params* params, void* U,
+                               int64_t ldu, double* S, void* V, int64_t ldv,
+                               isvd_svd_info* info, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Building blocks of Algorithm 1, exported for callers that drive their own
+ * iteration and for kernel-level tests.
+ * ------------------------------------------------------------------------ */
+
+/* rows x cols block of N(0,1) draws: Philox4x32-10 (Salmon et al., SC 2011),
+ * pair g of row-major entries uses counter (g, 0) and key `seed`; two 53-bit
+ * uniforms per pair, Box-Muller in FP64, rounded to `precision`.  Stands in
+ * for Algorithm 1's Gaussian start block.  Enqueued only. */
+isvd_status isvd_gaussian_block(int64_t rows, int64_t cols, uint64_t seed, isvd_precision precision,
+                                void* out, int64_t ld, void* stream);
+
+/* In place Q <- Y R^-1 with Y = Q R, R upper triangular with positive
+ * diagonal (the orthonormalisation of Algorithm 2, right, run twice:
+ * CholeskyQR2).  Gram Y^T Y and Cholesky in FP64, the apply in the block's
+ * precision.  R_out: optional device l x l FP64 row-major output (the
+ * product of both passes' factors).  Synchronises the stream.
+ * Errors: ISVD_E_INVALID, ISVD_E_NOT_SPD (Gram not positive definite). */
+isvd_status isvd_orthonormalize(int64_t rows, int64_t cols, isvd_precision precision, void* Y,
+                                int64_t ldy, double* R_out, void* stream);
+
+/* C = A^T B, A rows x m, B rows x p (same precision, leading dimensions lda,
+ * ldb), C m x p FP64 row-major (ldc), products formed exactly and summed in
+ * FP64 in a fixed order.  Enqueued only. */
+isvd_status isvd_gram(int64_t rows, int64_t m, int64_t p, isvd_precision precision, const void* A,
+                      int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc, void* stream);
+
+/* SVD of a small n x n FP64 matrix (n <= 1024) by one-sided Jacobi:
+ * A = Uo diag(s) Vo^T, s descending.  All device, row-major, leading dim n.
+ * The small Rayleigh-Ritz SVD of Algorithm 1 (its svd of B).  Enqueued only. */
+isvd_status isvd_small_svd(int64_t n, const double* A, double* Uo, double* s, double* Vo,
+                           void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start (not in the paper): a 16 -> 128 -> 128 -> k MLP with
+ * GELU maps per-node structural features to the first k columns of the
+ * start block; the remaining p columns stay Gaussian.
+ * ------------------------------------------------------------------------ */
+
+typedef struct isvd_warmstart isvd_warmstart;
+
+/* n x 16 FP32 features of the column-side nodes of an NE operator:
+ * log1p(d), log1p(T^j d) j=1..8, log1p((T^T)^j 1) j=1..7, each column
+ * z-scored (a column with deviation <= 1e-9 (1 + |mean|) becomes 0).
+ * F is device, row-major, leading dimension 16.  Synchronises. */
+isvd_status isvd_ws_features(isvd_operator* op, float* F, void* stream);
+
+/* New network with output width k; weights N(0, 1/fan_in) from Philox
+ * `seed`, biases 0, Adam state zero. */
+isvd_status isvd_ws_create(int k, uint64_t seed, isvd_warmstart** out);
+void isvd_ws_destroy(isvd_warmstart* ws);
+/* Total parameter count and its host layout: W1 (16x128), b1, W2 (128x128),
+ * b2, W3 (128xk), b3, row-major, concatenated, float. */
+int64_t isvd_ws_num_params(const isvd_warmstart* ws);
+isvd_status isvd_ws_get_params(const isvd_warmstart* ws, float* host_out);
+isvd_status isvd_ws_set_params(isvd_warmstart* ws, const float* host_in);
+
+/* Z = MLP(F): F n x 16 (ld 16), Z n x k (ld ldz), both FP32 device. Enqueued only. */
+isvd_status isvd_ws_forward(isvd_warmstart* ws, int64_t n, const float* F, float* Z, int64_t ldz,
+                            void* stream);
+
+/* Loss and parameter gradient for one graph: forward, subspace loss
+ * L = tr((Z^T Z)^-1 Z^T (I - V V^T) Z) / k against orthonormal V (n x k,
+ * ld ldv, FP32 device), backward.  grad_out: optional host array of
+ * isvd_ws_num_params floats.  loss_out: host.  If lr > 0 an Adam step
+ * (beta1 0.9, beta2 0.999, eps 1e-8) is applied.  Synchronises. */
+isvd_status isvd_ws_train_step(isvd_warmstart* ws, int64_t n, const float* F, const float* V,
+                               int64_t ldv, double lr, double* loss_out, float* grad_out,
+                               void* stream);
+
+/* Start block for isvd_truncated_svd from the network: omega (n x (k+p),
+ * ld ld_omega, operator precision) = [MLP(F), Gaussian(seed) p columns].
+ * Falls back to an all-Gaussian block (and sets *used_fallback = 1) when the
+ * network output is not finite or not of full column rank.  Synchronises. */
+isvd_status isvd_ws_omega(isvd_warmstart* ws, isvd_operator* op, const float* F, int p,
+                          uint64_t seed, void* omega, int64_t ld_omega, int* used_fallback,
+                          void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISVD_H */

@@ -1,0 +1,200 @@
+// extern "C" entry points: argument checks, exception barrier, last-error text.
+#include <string>
+
+#include "operator.h"
+
+namespace isvd {
+
+isvd_status truncated_svd(isvd_operator* op, const isvd_svd_params* prm, void* U, int64_t ldu, double* S,
+                          void* V, int64_t ldv, isvd_svd_info* info, hipStream_t stream);
+template <typename T>
+void orthonormalize_block(int64_t rows, int cols, T* Y, int64_t ld, double* Rout, hipStream_t stream);
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+template <typename F>
+isvd_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return ISVD_E_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return ISVD_E_INVALID;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return ISVD_E_INVALID;
+  }
+}
+
+}  // namespace isvd
+
+using namespace isvd;
+
+extern "C" {
+
+const char* isvd_status_string(isvd_status s) {
+  switch (s) {
+    case ISVD_OK: return "ok";
+    case ISVD_E_INVALID: return "invalid argument";
+    case ISVD_E_OOM: return "out of device memory";
+    case ISVD_E_HIP: return "HIP runtime error";
+    case ISVD_E_NOT_SPD: return "Cholesky breakdown (Gram matrix not positive definite)";
+    case ISVD_E_NOT_CONVERGED: return "tolerance not reached";
+    case ISVD_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* isvd_last_error(void) { return g_last_error.c_str(); }
+
+const char* isvd_version(void) { return "isvd-mi355x 0.1 (gfx950)"; }
+
+isvd_status isvd_create_operator(const isvd_graph* graph, const isvd_design* design, isvd_precision precision,
+                                 void* stream, isvd_operator** out) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(out, ISVD_E_INVALID, "null output pointer");
+    *out = nullptr;
+    auto* op = new isvd_operator();
+    try {
+      create_operator(graph, design, precision, static_cast<hipStream_t>(stream), op);
+    } catch (...) {
+      delete op;
+      throw;
+    }
+    *out = op;
+    return ISVD_OK;
+  });
+}
+
+void isvd_destroy_operator(isvd_operator* op) {
+  if (!op) return;
+  (void)hipDeviceSynchronize();
+  delete op;
+}
+
+isvd_status isvd_operator_shape(const isvd_operator* op, int64_t* rows, int64_t* cols) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(op && rows && cols, ISVD_E_INVALID, "null argument");
+    *rows = op->rows;
+    *cols = op->cols;
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_matmul_block(isvd_operator* op, int transpose, const void* Y, int64_t ldy, int64_t ncols,
+                              void* out, int64_t ldo, void* stream) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(op && Y && out, ISVD_E_INVALID, "null argument");
+    ISVD_CHECK(ncols >= 1 && ncols <= 1024, ISVD_E_INVALID, "ncols must be in [1, 1024]");
+    ISVD_CHECK(ldy >= ncols && ldo >= ncols, ISVD_E_INVALID, "leading dimension smaller than ncols");
+    ISVD_CHECK(Y != out, ISVD_E_INVALID, "Y and out must not overlap");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool t = transpose != 0;
+    const int nc = static_cast<int>(ncols);
+    switch (op->prec) {
+      case ISVD_FP64:
+        apply_operator<double>(op, t, static_cast<const double*>(Y), ldy, nc, static_cast<double*>(out), ldo, s);
+        break;
+      case ISVD_FP32:
+        apply_operator<float>(op, t, static_cast<const float*>(Y), ldy, nc, static_cast<float*>(out), ldo, s);
+        break;
+      default:
+        apply_operator<bf16>(op, t, static_cast<const bf16*>(Y), ldy, nc, static_cast<bf16*>(out), ldo, s);
+        break;
+    }
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_truncated_svd(isvd_operator* op, const isvd_svd_params* params, void* U, int64_t ldu, double* S,
+                               void* V, int64_t ldv, isvd_svd_info* info, void* stream) {
+  return guarded([&]() -> isvd_status {
+    return truncated_svd(op, params, U, ldu, S, V, ldv, info, static_cast<hipStream_t>(stream));
+  });
+}
+
+isvd_status isvd_gaussian_block(int64_t rows, int64_t cols, uint64_t seed, isvd_precision precision, void* out,
+                                int64_t ld, void* stream) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(out && rows >= 0 && cols >= 0 && ld >= cols, ISVD_E_INVALID, "bad block");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (precision) {
+      case ISVD_FP64: launch_gaussian<double>(rows, cols, seed, static_cast<double*>(out), ld, s); break;
+      case ISVD_FP32: launch_gaussian<float>(rows, cols, seed, static_cast<float*>(out), ld, s); break;
+      case ISVD_BF16: launch_gaussian<bf16>(rows, cols, seed, static_cast<bf16*>(out), ld, s); break;
+      default: throw Error{ISVD_E_INVALID, "bad precision"};
+    }
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_orthonormalize(int64_t rows, int64_t cols, isvd_precision precision, void* Y, int64_t ldy,
+                                double* R_out, void* stream) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(Y && cols >= 1 && cols <= 512 && rows >= cols && ldy >= cols, ISVD_E_INVALID,
+               "need 1 <= cols <= min(rows, 512) and ldy >= cols");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int c = static_cast<int>(cols);
+    switch (precision) {
+      case ISVD_FP64: orthonormalize_block<double>(rows, c, static_cast<double*>(Y), ldy, R_out, s); break;
+      case ISVD_FP32: orthonormalize_block<float>(rows, c, static_cast<float*>(Y), ldy, R_out, s); break;
+      case ISVD_BF16: orthonormalize_block<bf16>(rows, c, static_cast<bf16*>(Y), ldy, R_out, s); break;
+      default: throw Error{ISVD_E_INVALID, "bad precision"};
+    }
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_gram(int64_t rows, int64_t m, int64_t p, isvd_precision precision, const void* A, int64_t lda,
+                      const void* B, int64_t ldb, double* C, int64_t ldc, void* stream) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(A && B && C && rows >= 0 && m >= 1 && p >= 1 && m <= 2048 && p <= 2048, ISVD_E_INVALID,
+               "bad gram arguments");
+    ISVD_CHECK(lda >= m && ldb >= p && ldc >= p, ISVD_E_INVALID, "leading dimension too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf work;
+    work.ensure(gram_workspace_doubles(rows, static_cast<int>(m), static_cast<int>(p)) * sizeof(double));
+    const bool same = (A == B) && (m == p) && (lda == ldb);
+    switch (precision) {
+      case ISVD_FP64:
+        launch_gram<double>(rows, static_cast<int>(m), static_cast<int>(p), static_cast<const double*>(A), lda,
+                            static_cast<const double*>(B), ldb, same, C, ldc, work.as<double>(), s);
+        break;
+      case ISVD_FP32:
+        launch_gram<float>(rows, static_cast<int>(m), static_cast<int>(p), static_cast<const float*>(A), lda,
+                           static_cast<const float*>(B), ldb, same, C, ldc, work.as<double>(), s);
+        break;
+      case ISVD_BF16:
+        launch_gram<bf16>(rows, static_cast<int>(m), static_cast<int>(p), static_cast<const bf16*>(A), lda,
+                          static_cast<const bf16*>(B), ldb, same, C, ldc, work.as<double>(), s);
+        break;
+      default: throw Error{ISVD_E_INVALID, "bad precision"};
+    }
+    ISVD_HIP(hipStreamSynchronize(s));  // the workspace is freed on return
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_small_svd(int64_t n, const double* A, double* Uo, double* s, double* Vo, void* stream) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(A && Uo && s && Vo && n >= 1 && n <= 1024, ISVD_E_INVALID, "bad small svd arguments");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    DevBuf work;
+    work.ensure(jacobi_workspace_doubles(static_cast<int>(n)) * sizeof(double));
+    launch_jacobi_svd(static_cast<int>(n), A, n, Uo, s, Vo, work.as<double>(), nullptr, st);
+    ISVD_HIP(hipStreamSynchronize(st));
+    return ISVD_OK;
+  });
+}
+
+}  // extern "C"

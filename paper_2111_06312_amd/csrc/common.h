@@ -1,0 +1,132 @@
+// Shared device/host helpers for the implicit-SVD library (gfx950 / CDNA4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "isvd.h"
+
+namespace isvd {
+
+// ---------------------------------------------------------------- errors
+
+void set_last_error(const std::string& msg);
+
+struct Error {
+  isvd_status code;
+  std::string msg;
+};
+
+#define ISVD_HIP(expr)                                                              \
+  do {                                                                              \
+    hipError_t _e = (expr);                                                         \
+    if (_e != hipSuccess) {                                                         \
+      throw ::isvd::Error{_e == hipErrorOutOfMemory ? ISVD_E_OOM : ISVD_E_HIP,      \
+                          std::string(#expr) + ": " + hipGetErrorString(_e)};       \
+    }                                                                               \
+  } while (0)
+
+#define ISVD_CHECK(cond, code, msg)                                                 \
+  do {                                                                              \
+    if (!(cond)) throw ::isvd::Error{code, msg};                                    \
+  } while (0)
+
+#define ISVD_LAUNCH_CHECK() ISVD_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- bf16
+
+// Brain float stored as its 16-bit pattern.
+struct bf16 {
+  uint16_t bits;
+};
+
+__host__ __device__ inline float bf16_to_float(uint16_t b) {
+  union { uint32_t u; float f; } v;
+  v.u = static_cast<uint32_t>(b) << 16;
+  return v.f;
+}
+
+// Round to nearest, ties to even.  NaN stays NaN (quiet).
+__host__ __device__ inline uint16_t float_to_bf16(float f) {
+  union { uint32_t u; float f; } v;
+  v.f = f;
+  uint32_t u = v.u;
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return static_cast<uint16_t>((u >> 16) | 0x40u);
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return static_cast<uint16_t>(u >> 16);
+}
+
+// Element conversions between storage types and compute types.
+template <typename T> struct Elem;
+template <> struct Elem<double> {
+  __device__ static inline double load(const double* p) { return *p; }
+  __device__ static inline void store(double* p, double v) { *p = v; }
+  __device__ static inline double to_d(double v) { return v; }
+};
+template <> struct Elem<float> {
+  __device__ static inline float load(const float* p) { return *p; }
+  __device__ static inline void store(float* p, float v) { *p = v; }
+};
+template <> struct Elem<bf16> {
+  __device__ static inline float load(const bf16* p) { return bf16_to_float(p->bits); }
+  __device__ static inline void store(bf16* p, float v) { p->bits = float_to_bf16(v); }
+};
+
+// Compute type used for a storage type: FP64 stays FP64, FP32 and BF16 compute in FP32.
+template <typename T> struct ComputeOf { using type = float; };
+template <> struct ComputeOf<double> { using type = double; };
+
+template <typename A, typename B>
+__device__ inline A cvt(B v) { return static_cast<A>(v); }
+
+inline size_t elem_size(isvd_precision p) {
+  return p == ISVD_FP64 ? 8 : (p == ISVD_FP32 ? 4 : 2);
+}
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
+
+// ---------------------------------------------------------------- wave helpers
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline float wave_sum(float v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- device buffers
+
+// Owning device allocation (hipMalloc / hipFree).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t n) {
+    if (n <= bytes) return;
+    release();
+    ISVD_HIP(hipMalloc(&p, n));
+    bytes = n;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace isvd

@@ -1,0 +1,93 @@
+// Dense kernels on tall-skinny blocks and on small l x l FP64 matrices.
+#pragma once
+
+#include "common.h"
+
+namespace isvd {
+
+// ---------------------------------------------------------------- Gram C = A^T B (FP64)
+
+// Workspace (doubles) needed by launch_gram for an m x p result.
+size_t gram_workspace_doubles(int64_t rows, int m, int p);
+
+// C (m x p, FP64, ldc) = A^T B with A rows x m, B rows x p; `same` means B == A
+// (only the upper tile triangle is computed and mirrored).  Partial sums per
+// row slice are reduced in a fixed order.
+template <typename T>
+void launch_gram(int64_t rows, int m, int p, const T* A, int64_t lda, const T* B, int64_t ldb,
+                 bool same, double* C, int64_t ldc, double* work, hipStream_t stream);
+
+// Feature-side variant: A of type TA (features), B of type TB.
+template <typename TA, typename TB>
+void launch_gram2(int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
+                  double* C, int64_t ldc, double* work, hipStream_t stream);
+
+// ---------------------------------------------------------------- tall GEMM
+
+enum class GemmEpi { Store = 0, ColNorm2 = 1 };
+
+// C (M x N) = alpha * [A1 | A2] * B + beta * C   (A2 optional: K2 = 0)
+// A1: M x K1 (ld lda1), A2: M x K2 (ld lda2), storage type T; B: (K1+K2) x N
+// compute type (float for float/bf16 storage, double for double), ld ldb.
+// With ColNorm2 nothing is stored; colnorm (N doubles) receives sum_rows C^2
+// (two-stage reduction through `work`, gemm_colnorm_workspace doubles).
+template <typename T>
+void launch_gemm_tall(int64_t M, int N, int K1, const T* A1, int64_t lda1, int K2, const T* A2,
+                      int64_t lda2, const typename ComputeOf<T>::type* B, int64_t ldb, T* C,
+                      int64_t ldc, double alpha, double beta, GemmEpi epi, double* colnorm,
+                      double* work, hipStream_t stream);
+size_t gemm_colnorm_workspace(int64_t M, int N);
+
+// ---------------------------------------------------------------- Cholesky / TRSM
+
+// Padded size used for l x l factors (multiple of 16).
+__host__ __device__ inline int pad16(int l) { return (l + 15) / 16 * 16; }
+
+// Single-workgroup blocked Cholesky G = R^T R of an l x l SPD FP64 matrix.
+// G: l x l row-major ldg.  Outputs (padded lp = pad16(l), row-major ld lp):
+//   R64  : upper factor (lower triangle and padding set to the identity pattern)
+//   Rc   : R in compute type C (for the tall solve), Dinv_c: inverses of the
+//          16 x 16 diagonal tiles in compute type (lp/16 tiles, 256 entries each)
+//   flag : set to 1 on breakdown (pivot <= rel_tol * original diagonal or not finite)
+// `shift` is added to the diagonal before factorising.
+template <typename C>
+void launch_cholesky(int l, const double* G, int64_t ldg, double shift, double rel_tol, double* R64,
+                     C* Rc, C* Dinv_c, int* flag, hipStream_t stream);
+
+// In place Y <- Y R^-1 (rows x l block, storage T, ld), R/Dinv from launch_cholesky.
+template <typename T>
+void launch_trsm_tall(int64_t rows, int l, T* Y, int64_t ld, const typename ComputeOf<T>::type* Rc,
+                      const typename ComputeOf<T>::type* Dinv, hipStream_t stream);
+
+// C = A * B for upper-triangular l x l FP64 matrices (padded lp, ld lp).
+void launch_upper_mult(int l, const double* A, const double* B, double* C, int64_t ld,
+                       hipStream_t stream);
+
+// ---------------------------------------------------------------- small SVD
+
+size_t jacobi_workspace_doubles(int n);
+// A (n x n, FP64 row-major lda) = U diag(s) V^T; U, V n x n row-major (ld n), s descending.
+void launch_jacobi_svd(int n, const double* A, int64_t lda, double* U, double* s, double* V,
+                       double* work, int* sweeps_out, hipStream_t stream);
+
+// ---------------------------------------------------------------- misc
+
+template <typename T>
+void launch_gaussian(int64_t rows, int64_t cols, uint64_t seed, T* out, int64_t ld, hipStream_t stream);
+
+// dst (rows x cols, type D) = src (type S), any lds.
+template <typename D, typename S>
+void launch_convert(int64_t rows, int64_t cols, const S* src, int64_t lds, D* dst, int64_t ldd,
+                    hipStream_t stream);
+
+// Pack the residual right operand B2 = [U_R(:, :k); -Z_R(:, :k) diag(s)] (2l x k, compute type).
+template <typename C>
+void launch_pack_residual_rhs(int l, int k, const double* UR, const double* ZR, const double* s,
+                              int64_t ld, C* B, hipStream_t stream);
+
+// Right-side residual norms |R_c z_i - s_i u_{R,i}|^2 for i < k (FP64, small).
+void launch_small_residual(int l, int k, const double* Rc, int64_t ldr, const double* ZR,
+                           const double* UR, int64_t ldu, const double* s, double* out,
+                           hipStream_t stream);
+
+}  // namespace isvd

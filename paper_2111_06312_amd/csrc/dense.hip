@@ -1,0 +1,801 @@
+// Dense kernels: FP64-MFMA Gram, MFMA tall GEMM, blocked Cholesky, tall
+// triangular solve, one-sided Jacobi SVD, Philox Gaussian block.
+//
+// MFMA operand layout used throughout (16x16x4, FP32 and FP64): for lane t,
+// the A operand is A[t % 16][t / 16] and the B operand is B[t / 16][t % 16].
+// Accumulator value r (0..3) of lane t is D[row][t % 16] with
+// row = 4 (t / 16) + r for FP32 and row = t / 16 + 4 r for FP64 (drow below;
+// measured on gfx950).
+#include "dense.h"
+
+namespace isvd {
+
+namespace {
+
+__device__ inline v4f mfma4(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline v4d mfma4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <typename C> __device__ inline int drow(int lk, int r);
+template <> __device__ inline int drow<float>(int lk, int r) { return 4 * lk + r; }
+template <> __device__ inline int drow<double>(int lk, int r) { return lk + 4 * r; }
+
+template <typename C> struct Acc4;
+template <> struct Acc4<float> { using type = v4f; };
+template <> struct Acc4<double> { using type = v4d; };
+
+template <typename C, typename T>
+__device__ inline C ld_as(const T* p) { return static_cast<C>(Elem<T>::load(p)); }
+
+// ============================================================ Gram
+
+constexpr int kGramWaves = 4;
+constexpr int kGramTPW = 8;  // tiles per wave
+constexpr int kGramTPB = kGramWaves * kGramTPW;
+constexpr int kGramMaxParts = 256;
+
+__device__ inline void decode_tile(int idx, bool same, int tm, int tp, int& ti, int& tj) {
+  if (same) {
+    int i = 0;
+    while (idx >= tm - i) {
+      idx -= tm - i;
+      ++i;
+    }
+    ti = i;
+    tj = i + idx;
+  } else {
+    ti = idx / tp;
+    tj = idx % tp;
+  }
+}
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void gram_partial_kernel(int64_t rows, int m, int p, const TA* A,
+                                                           int64_t lda, const TB* B, int64_t ldb,
+                                                           int same, int tm, int tp, int ntiles,
+                                                           int64_t rows_per_block, int rb,
+                                                           double* partial, int mp, int pp) {
+  extern __shared__ double gsm[];
+  double* As = gsm;
+  double* Bs = same ? gsm : gsm + rb * mp;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int ti[kGramTPW], tj[kGramTPW];
+  bool act[kGramTPW];
+  v4d acc[kGramTPW];
+#pragma unroll
+  for (int t = 0; t < kGramTPW; ++t) {
+    const int idx = blockIdx.y * kGramTPB + wave + kGramWaves * t;
+    act[t] = idx < ntiles;
+    ti[t] = tj[t] = 0;
+    if (act[t]) decode_tile(idx, same, tm, tp, ti[t], tj[t]);
+    acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+  const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int64_t base = r0; base < r1; base += rb) {
+    __syncthreads();
+    for (int f = threadIdx.x; f < rb * mp; f += blockDim.x) {
+      const int r = f / mp, c = f - r * mp;
+      const int64_t row = base + r;
+      As[f] = (row < r1 && c < m) ? ld_as<double>(A + row * lda + c) : 0.0;
+    }
+    if (!same) {
+      for (int f = threadIdx.x; f < rb * pp; f += blockDim.x) {
+        const int r = f / pp, c = f - r * pp;
+        const int64_t row = base + r;
+        Bs[f] = (row < r1 && c < p) ? ld_as<double>(B + row * ldb + c) : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int kk = 0; kk < rb / 4; ++kk) {
+      const int kr = kk * 4 + lk;
+#pragma unroll
+      for (int t = 0; t < kGramTPW; ++t) {
+        if (act[t]) {
+          const double a = As[kr * mp + ti[t] * 16 + li];
+          const double b = Bs[kr * pp + tj[t] * 16 + li];
+          acc[t] = mfma4(a, b, acc[t]);
+        }
+      }
+    }
+  }
+  double* part = partial + static_cast<int64_t>(blockIdx.x) * mp * pp;
+#pragma unroll
+  for (int t = 0; t < kGramTPW; ++t) {
+    if (!act[t]) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      part[static_cast<int64_t>(ti[t] * 16 + drow<double>(lk, r)) * pp + tj[t] * 16 + li] = acc[t][r];
+  }
+}
+
+__global__ void gram_reduce_kernel(int m, int p, int nparts, const double* partial, int mp, int pp,
+                                   int same, double* C, int64_t ldc) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(m) * p) return;
+  const int a = static_cast<int>(idx / p), b = static_cast<int>(idx % p);
+  int sa = a, sb = b;
+  if (same && (a >> 4) > (b >> 4)) {
+    sa = b;
+    sb = a;
+  }
+  double s = 0.0;
+  const int64_t stride = static_cast<int64_t>(mp) * pp;
+  const int64_t off = static_cast<int64_t>(sa) * pp + sb;
+  for (int q = 0; q < nparts; ++q) s += partial[q * stride + off];
+  C[static_cast<int64_t>(a) * ldc + b] = s;
+}
+
+struct GramPlan {
+  int mp, pp, tm, tp, ntiles, rb, nparts, groups;
+  int64_t rows_per_block;
+  size_t lds;
+};
+
+GramPlan plan_gram(int64_t rows, int m, int p, bool same) {
+  GramPlan g;
+  g.mp = pad16(m);
+  g.pp = pad16(p);
+  g.tm = g.mp / 16;
+  g.tp = g.pp / 16;
+  g.ntiles = same ? g.tm * (g.tm + 1) / 2 : g.tm * g.tp;
+  const int cols = g.mp + (same ? 0 : g.pp);
+  g.rb = 16;
+  while (g.rb > 4 && static_cast<size_t>(g.rb) * cols * 8 > 64 * 1024) g.rb /= 2;
+  g.lds = static_cast<size_t>(g.rb) * cols * 8;
+  const int64_t want = ceil_div(rows > 0 ? rows : 1, kGramMaxParts);
+  g.rows_per_block = round_up(want < 64 ? 64 : want, g.rb);
+  g.nparts = static_cast<int>(ceil_div(rows > 0 ? rows : 1, g.rows_per_block));
+  g.groups = static_cast<int>(ceil_div(g.ntiles, kGramTPB));
+  return g;
+}
+
+template <typename TA, typename TB>
+void gram_impl(int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
+               bool same, double* C, int64_t ldc, double* work, hipStream_t stream) {
+  const GramPlan g = plan_gram(rows, m, p, same);
+  hipLaunchKernelGGL((gram_partial_kernel<TA, TB>), dim3(g.nparts, g.groups), dim3(256), g.lds,
+                     stream, rows, m, p, A, lda, B, ldb, same ? 1 : 0, g.tm, g.tp, g.ntiles,
+                     g.rows_per_block, g.rb, work, g.mp, g.pp);
+  ISVD_LAUNCH_CHECK();
+  const int64_t total = static_cast<int64_t>(m) * p;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(total, 256))), dim3(256),
+                     0, stream, m, p, g.nparts, work, g.mp, g.pp, same ? 1 : 0, C, ldc);
+  ISVD_LAUNCH_CHECK();
+}
+
+// ============================================================ tall GEMM
+
+constexpr int kGemmBK = 16;
+
+template <typename T, typename C, int TN, int EPI>
+__global__ __launch_bounds__(256) void gemm_tall_kernel(int64_t M, int N, int K1, const T* A1,
+                                                        int64_t lda1, int K2, const T* A2,
+                                                        int64_t lda2, const C* B, int64_t ldb, T* Cm,
+                                                        int64_t ldc, C alpha, C beta,
+                                                        double* colpart, int64_t row_tiles) {
+  using V = typename Acc4<C>::type;
+  __shared__ C As[64][kGemmBK + 1];
+  __shared__ C Bs[kGemmBK][16 * TN];
+  __shared__ double red[4][16 * TN];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int col0 = blockIdx.y * 16 * TN;
+  const int K = K1 + K2;
+  double cn[TN];
+#pragma unroll
+  for (int t = 0; t < TN; ++t) cn[t] = 0.0;
+
+  for (int64_t bt = blockIdx.x; bt < row_tiles; bt += gridDim.x) {
+    const int64_t row0 = bt * 64;
+    V acc[TN];
+#pragma unroll
+    for (int t = 0; t < TN; ++t) acc[t] = V{0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += kGemmBK) {
+      __syncthreads();
+      for (int f = threadIdx.x; f < 64 * kGemmBK; f += 256) {
+        const int r = f / kGemmBK, c = f % kGemmBK;
+        const int64_t row = row0 + r;
+        const int kc = k0 + c;
+        C v = C(0);
+        if (row < M && kc < K)
+          v = kc < K1 ? ld_as<C>(A1 + row * lda1 + kc) : ld_as<C>(A2 + row * lda2 + (kc - K1));
+        As[r][c] = v;
+      }
+      for (int f = threadIdx.x; f < kGemmBK * 16 * TN; f += 256) {
+        const int r = f / (16 * TN), c = f % (16 * TN);
+        const int kc = k0 + r, col = col0 + c;
+        Bs[r][c] = (kc < K && col < N) ? B[static_cast<int64_t>(kc) * ldb + col] : C(0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kGemmBK / 4; ++kk) {
+        const C a = As[wave * 16 + li][kk * 4 + lk];
+#pragma unroll
+        for (int t = 0; t < TN; ++t) acc[t] = mfma4(a, Bs[kk * 4 + lk][t * 16 + li], acc[t]);
+      }
+    }
+    if constexpr (EPI == static_cast<int>(GemmEpi::Store)) {
+#pragma unroll
+      for (int t = 0; t < TN; ++t) {
+        const int col = col0 + t * 16 + li;
+        if (col >= N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = row0 + wave * 16 + drow<C>(lk, r);
+          if (row >= M) continue;
+          C v = alpha * acc[t][r];
+          if (beta != C(0)) v += beta * ld_as<C>(Cm + row * ldc + col);
+          Elem<T>::store(Cm + row * ldc + col, v);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < TN; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = row0 + wave * 16 + drow<C>(lk, r);
+          const double v = static_cast<double>(acc[t][r]);
+          if (row < M) cn[t] += v * v;
+        }
+    }
+  }
+  if constexpr (EPI == static_cast<int>(GemmEpi::ColNorm2)) {
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+      double s = cn[t];
+      s += __shfl_xor(s, 16, 64);
+      s += __shfl_xor(s, 32, 64);
+      if (lk == 0) red[wave][t * 16 + li] = s;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < 16 * TN; c += 256) {
+      const int col = col0 + c;
+      if (col < N) colpart[static_cast<int64_t>(blockIdx.x) * N + col] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void colpart_reduce_kernel(int nparts, int N, const double* part, double* out) {
+  __shared__ double s[256];
+  const int col = blockIdx.x;
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < nparts; q += 256) acc += part[static_cast<int64_t>(q) * N + col];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[col] = s[0];
+}
+
+constexpr int kColnormParts = 1024;
+
+template <typename T, typename C, int TN>
+void gemm_launch_tn(int64_t M, int N, int K1, const T* A1, int64_t lda1, int K2, const T* A2,
+                    int64_t lda2, const C* B, int64_t ldb, T* Cm, int64_t ldc, double alpha,
+                    double beta, GemmEpi epi, double* colnorm, double* work, hipStream_t stream) {
+  const int64_t row_tiles = ceil_div(M, 64);
+  const int ycb = static_cast<int>(ceil_div(N, 16 * TN));
+  if (epi == GemmEpi::Store) {
+    hipLaunchKernelGGL((gemm_tall_kernel<T, C, TN, 0>), dim3(static_cast<unsigned>(row_tiles), ycb),
+                       dim3(256), 0, stream, M, N, K1, A1, lda1, K2, A2, lda2, B, ldb, Cm, ldc,
+                       static_cast<C>(alpha), static_cast<C>(beta), nullptr, row_tiles);
+    ISVD_LAUNCH_CHECK();
+  } else {
+    const int parts = static_cast<int>(row_tiles < kColnormParts ? row_tiles : kColnormParts);
+    hipLaunchKernelGGL((gemm_tall_kernel<T, C, TN, 1>), dim3(parts, ycb), dim3(256), 0, stream, M, N,
+                       K1, A1, lda1, K2, A2, lda2, B, ldb, Cm, ldc, static_cast<C>(alpha),
+                       static_cast<C>(beta), work, row_tiles);
+    ISVD_LAUNCH_CHECK();
+    hipLaunchKernelGGL(colpart_reduce_kernel, dim3(N), dim3(256), 0, stream, parts, N, work, colnorm);
+    ISVD_LAUNCH_CHECK();
+  }
+}
+
+// ============================================================ Cholesky
+
+// Factor one 16 x 16 diagonal tile in registers: lane c (0..15) holds column c.
+// On return s[k] = R[k][c] (upper, zero below the diagonal) and x[k] = (R^-1)[k][c].
+__device__ inline void tile_cholesky(double (&s)[16], double (&x)[16], int c, double refv,
+                                     double rel_tol, int* bad) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < j; ++k) t += __shfl(s[k], j, 64) * s[k];
+    const double v = s[j] - t;
+    const double piv = __shfl(v, j, 64);
+    const double ref = __shfl(refv, j, 64);
+    if (!(piv > rel_tol * ref) || !isfinite(piv)) *bad = 1;
+    const double rjj = sqrt(piv > 0.0 ? piv : 1e-300);
+    s[j] = (c > j) ? v / rjj : (c == j ? rjj : 0.0);
+  }
+#pragma unroll
+  for (int i = 15; i >= 0; --i) {
+    double acc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = i + 1; k < 16; ++k) acc -= __shfl(s[i], k, 64) * x[k];
+    x[i] = acc / __shfl(s[i], i, 64);
+  }
+}
+
+template <typename C>
+__global__ __launch_bounds__(1024) void cholesky_kernel(int l, const double* G, int64_t ldg, double shift,
+                                                        double rel_tol, double* W, C* Rc, C* Dc, int* flag) {
+  const int lp = pad16(l), T = lp / 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  __shared__ double dinv_s[256];
+  __shared__ int bad;
+  for (int64_t idx = tid; idx < static_cast<int64_t>(lp) * lp; idx += blockDim.x) {
+    const int i = static_cast<int>(idx / lp), j = static_cast<int>(idx % lp);
+    double v = (i == j) ? 1.0 : 0.0;
+    if (i < l && j < l) v = G[static_cast<int64_t>(i) * ldg + j] + (i == j ? shift : 0.0);
+    W[idx] = v;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int J = 0; J < T; ++J) {
+    const int o = J * 16;
+    if (wave == 0) {
+      const int gi = o + li;
+      const double refv = gi < l ? fabs(G[static_cast<int64_t>(gi) * ldg + gi] + shift) : 1.0;
+      double s[16], x[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s[k] = W[static_cast<int64_t>(o + k) * lp + o + li];
+      int mybad = 0;
+      tile_cholesky(s, x, li, refv, rel_tol, &mybad);
+      if (mybad && lane == 0) bad = 1;
+      if (lane < 16) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          W[static_cast<int64_t>(o + k) * lp + o + li] = s[k];
+          dinv_s[k * 16 + li] = x[k];
+          Dc[J * 256 + k * 16 + li] = static_cast<C>(x[k]);
+        }
+      }
+    }
+    __syncthreads();
+    // panel: R_JK = Dinv^T W_JK, K > J
+    for (int K = J + 1 + wave; K < T; K += nw) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int kr = kk * 4 + lk;
+        const double a = dinv_s[kr * 16 + li];
+        const double b = W[static_cast<int64_t>(o + kr) * lp + K * 16 + li];
+        acc = mfma4(a, b, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) W[static_cast<int64_t>(o + drow<double>(lk, r)) * lp + K * 16 + li] = acc[r];
+    }
+    __syncthreads();
+    // trailing update: W_KK' -= R_JK^T R_JK', J < K <= K'
+    const int rem = T - J - 1;
+    const int pairs = rem * (rem + 1) / 2;
+    for (int pi = wave; pi < pairs; pi += nw) {
+      int a_ = 0, q = pi;
+      while (q >= rem - a_) {
+        q -= rem - a_;
+        ++a_;
+      }
+      const int K = J + 1 + a_, K2 = K + q;
+      v4d acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = W[static_cast<int64_t>(K * 16 + drow<double>(lk, r)) * lp + K2 * 16 + li];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int kr = kk * 4 + lk;
+        const double a = W[static_cast<int64_t>(o + kr) * lp + K * 16 + li];
+        const double b = W[static_cast<int64_t>(o + kr) * lp + K2 * 16 + li];
+        acc = mfma4(-a, b, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) W[static_cast<int64_t>(K * 16 + drow<double>(lk, r)) * lp + K2 * 16 + li] = acc[r];
+    }
+    __syncthreads();
+  }
+  for (int64_t idx = tid; idx < static_cast<int64_t>(lp) * lp; idx += blockDim.x) {
+    const int i = static_cast<int>(idx / lp), j = static_cast<int>(idx % lp);
+    double v = W[idx];
+    if (i > j) {
+      v = 0.0;
+      W[idx] = 0.0;
+    }
+    Rc[idx] = static_cast<C>(v);
+  }
+  if (tid == 0) *flag = bad;
+}
+
+// ============================================================ tall triangular solve
+
+template <typename T, typename C>
+__global__ void trsm_tall_kernel(int64_t rows, int l, T* Y, int64_t ld, const C* Rc, const C* Dc) {
+  using V = typename Acc4<C>::type;
+  extern __shared__ char tsm[];
+  const int lp = pad16(l), TT = lp / 16, lq = lp + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  C* Qs = reinterpret_cast<C*>(tsm) + static_cast<int64_t>(wave) * 16 * lq;
+  const int64_t row0 = (static_cast<int64_t>(blockIdx.x) * nwave + wave) * 16;
+  for (int K = 0; K < TT; ++K) {
+    V acc;
+    const int col = K * 16 + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + drow<C>(lk, r);
+      acc[r] = (row < rows && col < l) ? ld_as<C>(Y + row * ld + col) : C(0);
+    }
+    for (int J = 0; J < K; ++J) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const C a = Qs[li * lq + J * 16 + kk * 4 + lk];
+        const C b = Rc[static_cast<int64_t>(J * 16 + kk * 4 + lk) * lp + K * 16 + li];
+        acc = mfma4(-a, b, acc);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Qs[drow<C>(lk, r) * lq + K * 16 + li] = acc[r];
+    __syncthreads();
+    V q = V{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const C a = Qs[li * lq + K * 16 + kk * 4 + lk];
+      const C b = Dc[K * 256 + (kk * 4 + lk) * 16 + li];
+      q = mfma4(a, b, q);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Qs[drow<C>(lk, r) * lq + K * 16 + li] = q[r];
+      const int64_t row = row0 + drow<C>(lk, r);
+      if (row < rows && col < l) Elem<T>::store(Y + row * ld + col, q[r]);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void upper_mult_kernel(int lp, const double* A, const double* B, double* Cm, int64_t ld) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(lp) * lp) return;
+  const int i = static_cast<int>(idx / lp), j = static_cast<int>(idx % lp);
+  double s = 0.0;
+  for (int k = i; k <= j; ++k) s += A[static_cast<int64_t>(i) * ld + k] * B[static_cast<int64_t>(k) * ld + j];
+  Cm[static_cast<int64_t>(i) * ld + j] = (i <= j) ? s : 0.0;
+}
+
+// ============================================================ one-sided Jacobi SVD
+
+constexpr int kJacobiMaxN = 1024;
+constexpr int kJacobiPerLane = kJacobiMaxN / 16;
+
+// Each pair of columns is handled by a quarter wave (16 lanes).
+__global__ __launch_bounds__(1024) void jacobi_kernel(int n, const double* A, int64_t lda, double* Uo,
+                                                      double* s, double* Vo, double* work, int* sweeps_out) {
+  const int np = n + (n & 1);
+  double* Wt = work;                                   // np x n
+  double* Jt = work + static_cast<int64_t>(np) * n;    // np x n
+  double* sig = Jt + static_cast<int64_t>(np) * n;     // np
+  int* rank = reinterpret_cast<int*>(sig + np);        // np
+  const int tid = threadIdx.x;
+  const int q16 = tid >> 4, ql = tid & 15, nq = blockDim.x >> 4;
+  __shared__ int rotated;
+  for (int64_t idx = tid; idx < static_cast<int64_t>(np) * n; idx += blockDim.x) {
+    const int p = static_cast<int>(idx / n), i = static_cast<int>(idx % n);
+    Wt[idx] = p < n ? A[static_cast<int64_t>(i) * lda + p] : 0.0;
+    Jt[idx] = (p == i) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const double tol = 2.0e-15;
+  int sweep = 0;
+  for (; sweep < 60; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < np - 1; ++r) {
+      for (int k = q16; k < np / 2; k += nq) {
+        const int a = (k == 0) ? 0 : ((k - 1 + r) % (np - 1)) + 1;
+        const int b = ((np - 2 - k + r) % (np - 1)) + 1;
+        double* wa = Wt + static_cast<int64_t>(a) * n;
+        double* wb = Wt + static_cast<int64_t>(b) * n;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = ql; i < n; i += 16) {
+          const double x = wa[i], y = wb[i];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+          al += __shfl_xor(al, off, 16);
+          be += __shfl_xor(be, off, 16);
+          ga += __shfl_xor(ga, off, 16);
+        }
+        if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t);
+          const double sn = c * t;
+          double* ja = Jt + static_cast<int64_t>(a) * n;
+          double* jb = Jt + static_cast<int64_t>(b) * n;
+          for (int i = ql; i < n; i += 16) {
+            const double x = wa[i], y = wb[i];
+            wa[i] = c * x - sn * y;
+            wb[i] = sn * x + c * y;
+            const double u = ja[i], v = jb[i];
+            ja[i] = c * u - sn * v;
+            jb[i] = sn * u + c * v;
+          }
+          if (ql == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  for (int p = q16; p < np; p += nq) {
+    const double* wp = Wt + static_cast<int64_t>(p) * n;
+    double acc = 0.0;
+    for (int i = ql; i < n; i += 16) acc += wp[i] * wp[i];
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+    if (ql == 0) sig[p] = sqrt(acc);
+  }
+  __syncthreads();
+  for (int p = tid; p < n; p += blockDim.x) {
+    const double sp = sig[p];
+    int rk = 0;
+    for (int q = 0; q < n; ++q) {
+      const double sq = sig[q];
+      rk += (sq > sp || (sq == sp && q < p)) ? 1 : 0;
+    }
+    rank[p] = rk;
+    s[rk] = sp;
+  }
+  __syncthreads();
+  for (int64_t idx = tid; idx < static_cast<int64_t>(n) * n; idx += blockDim.x) {
+    const int p = static_cast<int>(idx / n), i = static_cast<int>(idx % n);
+    const int rk = rank[p];
+    const double sp = sig[p];
+    Uo[static_cast<int64_t>(i) * n + rk] = sp > 0.0 ? Wt[idx] / sp : 0.0;
+    Vo[static_cast<int64_t>(i) * n + rk] = Jt[idx];
+  }
+  if (tid == 0 && sweeps_out) *sweeps_out = sweep;
+}
+
+// ============================================================ Philox Gaussian
+
+__device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t p0 = static_cast<uint64_t>(M0) * c[0];
+    const uint64_t p1 = static_cast<uint64_t>(M1) * c[2];
+    const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+    const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+template <typename T>
+__global__ void gaussian_kernel(int64_t rows, int64_t cols, uint64_t seed, T* out, int64_t ld) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t total = rows * cols;
+  if (2 * g >= total) return;
+  uint32_t c[4] = {static_cast<uint32_t>(g), static_cast<uint32_t>(static_cast<uint64_t>(g) >> 32), 0u, 0u};
+  philox10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+  const double two26 = 67108864.0, inv53 = 1.0 / 9007199254740992.0;
+  const double u1 = ((c[0] >> 5) * two26 + (c[1] >> 6) + 0.5) * inv53;
+  const double u2 = ((c[2] >> 5) * two26 + (c[3] >> 6) + 0.5) * inv53;
+  const double rad = sqrt(-2.0 * log(u1));
+  const double th = 6.283185307179586476925286766559 * u2;
+  const double z[2] = {rad * cos(th), rad * sin(th)};
+  for (int h = 0; h < 2; ++h) {
+    const int64_t e = 2 * g + h;
+    if (e >= total) break;
+    const int64_t r = e / cols, cc = e % cols;
+    Elem<T>::store(out + r * ld + cc, static_cast<typename ComputeOf<T>::type>(z[h]));
+  }
+}
+
+template <typename D, typename S>
+__global__ void convert_kernel(int64_t rows, int64_t cols, const S* src, int64_t lds, D* dst, int64_t ldd) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t r = idx / cols, c = idx % cols;
+  using CD = typename ComputeOf<D>::type;
+  Elem<D>::store(dst + r * ldd + c, static_cast<CD>(Elem<S>::load(src + r * lds + c)));
+}
+
+template <typename C>
+__global__ void pack_residual_rhs_kernel(int l, int k, const double* UR, const double* ZR, const double* s,
+                                         int64_t ld, C* B) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * l * k) return;
+  const int r = idx / k, c = idx % k;
+  const double v = r < l ? UR[static_cast<int64_t>(r) * ld + c] : -ZR[static_cast<int64_t>(r - l) * ld + c] * s[c];
+  B[idx] = static_cast<C>(v);
+}
+
+__global__ void small_residual_kernel(int l, int k, const double* Rc, int64_t ldr, const double* ZR,
+                                      const double* UR, int64_t ldu, const double* s, double* out) {
+  const int i = blockIdx.x;
+  if (i >= k) return;
+  double acc = 0.0;
+  for (int row = threadIdx.x; row < l; row += blockDim.x) {
+    double v = 0.0;
+    for (int c = row; c < l; ++c) v += Rc[static_cast<int64_t>(row) * ldr + c] * ZR[static_cast<int64_t>(c) * ldu + i];
+    v -= s[i] * UR[static_cast<int64_t>(row) * ldu + i];
+    acc += v * v;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
+}
+
+}  // namespace
+
+// ============================================================ host wrappers
+
+size_t gram_workspace_doubles(int64_t rows, int m, int p) {
+  const GramPlan g = plan_gram(rows, m, p, false);
+  return static_cast<size_t>(g.nparts) * g.mp * g.pp;
+}
+
+template <typename T>
+void launch_gram(int64_t rows, int m, int p, const T* A, int64_t lda, const T* B, int64_t ldb, bool same,
+                 double* C, int64_t ldc, double* work, hipStream_t stream) {
+  gram_impl<T, T>(rows, m, p, A, lda, B, ldb, same, C, ldc, work, stream);
+}
+template <typename TA, typename TB>
+void launch_gram2(int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
+                  double* C, int64_t ldc, double* work, hipStream_t stream) {
+  gram_impl<TA, TB>(rows, m, p, A, lda, B, ldb, false, C, ldc, work, stream);
+}
+template void launch_gram<double>(int64_t, int, int, const double*, int64_t, const double*, int64_t, bool, double*, int64_t, double*, hipStream_t);
+template void launch_gram<float>(int64_t, int, int, const float*, int64_t, const float*, int64_t, bool, double*, int64_t, double*, hipStream_t);
+template void launch_gram<bf16>(int64_t, int, int, const bf16*, int64_t, const bf16*, int64_t, bool, double*, int64_t, double*, hipStream_t);
+template void launch_gram2<double, double>(int64_t, int, int, const double*, int64_t, const double*, int64_t, double*, int64_t, double*, hipStream_t);
+template void launch_gram2<float, float>(int64_t, int, int, const float*, int64_t, const float*, int64_t, double*, int64_t, double*, hipStream_t);
+template void launch_gram2<float, bf16>(int64_t, int, int, const float*, int64_t, const bf16*, int64_t, double*, int64_t, double*, hipStream_t);
+template void launch_gram2<bf16, bf16>(int64_t, int, int, const bf16*, int64_t, const bf16*, int64_t, double*, int64_t, double*, hipStream_t);
+
+size_t gemm_colnorm_workspace(int64_t M, int N) {
+  (void)M;
+  return static_cast<size_t>(kColnormParts) * N;
+}
+
+template <typename T>
+void launch_gemm_tall(int64_t M, int N, int K1, const T* A1, int64_t lda1, int K2, const T* A2,
+                      int64_t lda2, const typename ComputeOf<T>::type* B, int64_t ldb, T* Cm,
+                      int64_t ldc, double alpha, double beta, GemmEpi epi, double* colnorm,
+                      double* work, hipStream_t stream) {
+  using C = typename ComputeOf<T>::type;
+  if (M <= 0 || N <= 0) return;
+  const int tiles = static_cast<int>(ceil_div(N, 16));
+  const int ncb = static_cast<int>(ceil_div(tiles, 8));
+  const int tn = static_cast<int>(ceil_div(tiles, ncb));
+  switch (tn) {
+#define ISVD_TN(X) \
+  case X: return gemm_launch_tn<T, C, X>(M, N, K1, A1, lda1, K2, A2, lda2, B, ldb, Cm, ldc, alpha, beta, epi, colnorm, work, stream);
+    ISVD_TN(1) ISVD_TN(2) ISVD_TN(3) ISVD_TN(4) ISVD_TN(5) ISVD_TN(6) ISVD_TN(7) ISVD_TN(8)
+#undef ISVD_TN
+    default: throw Error{ISVD_E_INVALID, "gemm: bad tile count"};
+  }
+}
+template void launch_gemm_tall<double>(int64_t, int, int, const double*, int64_t, int, const double*, int64_t, const double*, int64_t, double*, int64_t, double, double, GemmEpi, double*, double*, hipStream_t);
+template void launch_gemm_tall<float>(int64_t, int, int, const float*, int64_t, int, const float*, int64_t, const float*, int64_t, float*, int64_t, double, double, GemmEpi, double*, double*, hipStream_t);
+template void launch_gemm_tall<bf16>(int64_t, int, int, const bf16*, int64_t, int, const bf16*, int64_t, const float*, int64_t, bf16*, int64_t, double, double, GemmEpi, double*, double*, hipStream_t);
+
+template <typename C>
+void launch_cholesky(int l, const double* G, int64_t ldg, double shift, double rel_tol, double* R64,
+                     C* Rc, C* Dinv_c, int* flag, hipStream_t stream) {
+  hipLaunchKernelGGL((cholesky_kernel<C>), dim3(1), dim3(1024), 0, stream, l, G, ldg, shift, rel_tol,
+                     R64, Rc, Dinv_c, flag);
+  ISVD_LAUNCH_CHECK();
+}
+template void launch_cholesky<double>(int, const double*, int64_t, double, double, double*, double*, double*, int*, hipStream_t);
+template void launch_cholesky<float>(int, const double*, int64_t, double, double, double*, float*, float*, int*, hipStream_t);
+
+template <typename T>
+void launch_trsm_tall(int64_t rows, int l, T* Y, int64_t ld, const typename ComputeOf<T>::type* Rc,
+                      const typename ComputeOf<T>::type* Dinv, hipStream_t stream) {
+  using C = typename ComputeOf<T>::type;
+  if (rows <= 0) return;
+  const int waves = sizeof(C) == 8 ? 2 : 4;
+  const size_t lds = static_cast<size_t>(waves) * 16 * (pad16(l) + 1) * sizeof(C);
+  ISVD_CHECK(lds <= 160 * 1024, ISVD_E_INVALID, "trsm: block too wide");
+  const int64_t blocks = ceil_div(rows, 16 * waves);
+  hipLaunchKernelGGL((trsm_tall_kernel<T, C>), dim3(static_cast<unsigned>(blocks)), dim3(64 * waves), lds,
+                     stream, rows, l, Y, ld, Rc, Dinv);
+  ISVD_LAUNCH_CHECK();
+}
+template void launch_trsm_tall<double>(int64_t, int, double*, int64_t, const double*, const double*, hipStream_t);
+template void launch_trsm_tall<float>(int64_t, int, float*, int64_t, const float*, const float*, hipStream_t);
+template void launch_trsm_tall<bf16>(int64_t, int, bf16*, int64_t, const float*, const float*, hipStream_t);
+
+void launch_upper_mult(int l, const double* A, const double* B, double* Cm, int64_t ld, hipStream_t stream) {
+  const int lp = pad16(l);
+  const int64_t total = static_cast<int64_t>(lp) * lp;
+  hipLaunchKernelGGL(upper_mult_kernel, dim3(static_cast<unsigned>(ceil_div(total, 256))), dim3(256), 0,
+                     stream, lp, A, B, Cm, ld);
+  ISVD_LAUNCH_CHECK();
+}
+
+size_t jacobi_workspace_doubles(int n) {
+  const int np = n + (n & 1);
+  return 2 * static_cast<size_t>(np) * n + 2 * static_cast<size_t>(np) + 8;
+}
+
+void launch_jacobi_svd(int n, const double* A, int64_t lda, double* U, double* s, double* V, double* work,
+                       int* sweeps_out, hipStream_t stream) {
+  ISVD_CHECK(n >= 1 && n <= kJacobiMaxN, ISVD_E_INVALID, "small svd: n out of range");
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
+  ISVD_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_gaussian(int64_t rows, int64_t cols, uint64_t seed, T* out, int64_t ld, hipStream_t stream) {
+  const int64_t pairs = ceil_div(rows * cols, 2);
+  if (pairs == 0) return;
+  hipLaunchKernelGGL(gaussian_kernel<T>, dim3(static_cast<unsigned>(ceil_div(pairs, 256))), dim3(256), 0,
+                     stream, rows, cols, seed, out, ld);
+  ISVD_LAUNCH_CHECK();
+}
+template void launch_gaussian<double>(int64_t, int64_t, uint64_t, double*, int64_t, hipStream_t);
+template void launch_gaussian<float>(int64_t, int64_t, uint64_t, float*, int64_t, hipStream_t);
+template void launch_gaussian<bf16>(int64_t, int64_t, uint64_t, bf16*, int64_t, hipStream_t);
+
+template <typename D, typename S>
+void launch_convert(int64_t rows, int64_t cols, const S* src, int64_t lds, D* dst, int64_t ldd,
+                    hipStream_t stream) {
+  const int64_t total = rows * cols;
+  if (total == 0) return;
+  hipLaunchKernelGGL((convert_kernel<D, S>), dim3(static_cast<unsigned>(ceil_div(total, 256))), dim3(256),
+                     0, stream, rows, cols, src, lds, dst, ldd);
+  ISVD_LAUNCH_CHECK();
+}
+template void launch_convert<float, bf16>(int64_t, int64_t, const bf16*, int64_t, float*, int64_t, hipStream_t);
+template void launch_convert<bf16, float>(int64_t, int64_t, const float*, int64_t, bf16*, int64_t, hipStream_t);
+template void launch_convert<float, float>(int64_t, int64_t, const float*, int64_t, float*, int64_t, hipStream_t);
+template void launch_convert<double, double>(int64_t, int64_t, const double*, int64_t, double*, int64_t, hipStream_t);
+template void launch_convert<bf16, bf16>(int64_t, int64_t, const bf16*, int64_t, bf16*, int64_t, hipStream_t);
+template void launch_convert<float, double>(int64_t, int64_t, const double*, int64_t, float*, int64_t, hipStream_t);
+template void launch_convert<double, float>(int64_t, int64_t, const float*, int64_t, double*, int64_t, hipStream_t);
+
+template <typename C>
+void launch_pack_residual_rhs(int l, int k, const double* UR, const double* ZR, const double* s, int64_t ld,
+                              C* B, hipStream_t stream) {
+  hipLaunchKernelGGL((pack_residual_rhs_kernel<C>), dim3(static_cast<unsigned>(ceil_div(2 * l * k, 256))),
+                     dim3(256), 0, stream, l, k, UR, ZR, s, ld, B);
+  ISVD_LAUNCH_CHECK();
+}
+template void launch_pack_residual_rhs<float>(int, int, const double*, const double*, const double*, int64_t, float*, hipStream_t);
+template void launch_pack_residual_rhs<double>(int, int, const double*, const double*, const double*, int64_t, double*, hipStream_t);
+
+void launch_small_residual(int l, int k, const double* Rc, int64_t ldr, const double* ZR, const double* UR,
+                           int64_t ldu, const double* s, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(small_residual_kernel, dim3(k), dim3(256), 0, stream, l, k, Rc, ldr, ZR, UR, ldu, s, out);
+  ISVD_LAUNCH_CHECK();
+}
+
+}  // namespace isvd

@@ -1,0 +1,339 @@
+// Algorithm 1 (randomized SVD of an implicit matrix) on the GPU.
+//
+// One iteration t:   Y = M Qc;  Qr, Rr = CholQR2(Y);  W = M^T Qr;  Qc, Rc = CholQR2(W)
+// (the paper's loop body, its orthonormaliser being Algorithm 2's Cholesky
+// variant applied twice).  Rayleigh-Ritz after iteration t: B = W^T =
+// Rc^T Qc^T, so with Rc = U_R S Z_R^T (one-sided Jacobi, FP64) the triplets
+// are U = Qr Z_R, S, V = Qc U_R -- Algorithm 1's svd(B) and Q x U, with B
+// reduced to its l x l triangular factor.  Fixed mode runs q+1 iterations
+// (Algorithm 1 with iterations = q).  Tolerance mode checks the triplets of
+// iteration t during iteration t+1, whose first product M Qc gives M V for
+// free:  |M v_i - s_i u_i| = column i of [Y | Qr] [U_R; -Z_R S].
+#include <chrono>
+#include <vector>
+
+#include "operator.h"
+
+namespace isvd {
+
+namespace {
+
+struct SvdState {
+  int64_t r = 0, c = 0;
+  int k = 0, l = 0, lp = 0;
+  int64_t ld = 0;
+  // blocks (storage of the current phase)
+  DevBuf qc, w, qr, y;
+  // small FP64 matrices (padded lp x lp, ld lp)
+  DevBuf G, R1, R2, Rc, Rtmp, Rcc, Dc, flag, UR, ZR, sig, jac_work, rhs, left2, right2, gram_work, cn_work, sweeps;
+  int iterations = 0, applies = 0, bf16_iterations = 0, checks = 0, fallback = 0;
+  double residual = -1.0;
+  bool have_ritz = false;
+  int ritz_iter = -1;
+};
+
+template <typename T>
+void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, hipStream_t stream) {
+  using C = typename ComputeOf<T>::type;
+  const int l = st.l, lp = st.lp;
+  st.G.ensure(static_cast<size_t>(l) * l * sizeof(double));
+  st.R1.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
+  st.R2.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
+  st.Rcc.ensure(static_cast<size_t>(lp) * lp * sizeof(C));
+  st.Dc.ensure(static_cast<size_t>(lp) * 16 * sizeof(C));
+  st.flag.ensure(4 * sizeof(int));
+  st.gram_work.ensure(gram_workspace_doubles(rows, l, l) * sizeof(double));
+  double* Rp[3] = {st.R1.as<double>(), st.R2.as<double>(), nullptr};
+  int passes = 2;
+  for (int pass = 0; pass < passes; ++pass) {
+    double* Rdst = Rp[pass < 2 ? pass : 1];
+    if (pass == 2) {
+      // third pass after a shifted first pass: fold R2 into R1 first
+      st.Rtmp.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
+      launch_upper_mult(l, st.R2.as<double>(), st.R1.as<double>(), st.Rtmp.as<double>(), lp, stream);
+      ISVD_HIP(hipMemcpyAsync(st.R1.p, st.Rtmp.p, static_cast<size_t>(lp) * lp * sizeof(double),
+                              hipMemcpyDeviceToDevice, stream));
+    }
+    launch_gram<T>(rows, l, l, Y, st.ld, Y, st.ld, true, st.G.as<double>(), l, st.gram_work.as<double>(), stream);
+    launch_cholesky<C>(l, st.G.as<double>(), l, 0.0, 1e-14, Rdst, st.Rcc.as<C>(), st.Dc.as<C>(),
+                       st.flag.as<int>(), stream);
+    int flag = 0;
+    ISVD_HIP(hipMemcpyAsync(&flag, st.flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+    ISVD_HIP(hipStreamSynchronize(stream));
+    if (flag) {
+      // shifted Cholesky QR (Fukaya et al.): G + s I with s ~ 11 (m l + l (l+1)) u tr(G)
+      std::vector<double> g(static_cast<size_t>(l) * l);
+      double tr = 0.0;
+      ISVD_HIP(hipMemcpy(g.data(), st.G.p, g.size() * sizeof(double), hipMemcpyDeviceToHost));
+      for (int i = 0; i < l; ++i) tr += g[static_cast<size_t>(i) * l + i];
+      const double shift = 11.0 * (static_cast<double>(rows) * l + static_cast<double>(l) * (l + 1)) *
+                           1.1102230246251565e-16 * tr;
+      launch_cholesky<C>(l, st.G.as<double>(), l, shift, 0.0, Rdst, st.Rcc.as<C>(), st.Dc.as<C>(),
+                         st.flag.as<int>(), stream);
+      ISVD_HIP(hipMemcpyAsync(&flag, st.flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+      ISVD_HIP(hipStreamSynchronize(stream));
+      ISVD_CHECK(flag == 0 && tr > 0.0 && std::isfinite(tr), ISVD_E_NOT_SPD,
+                 "Cholesky breakdown: Gram matrix not positive definite even with a shift");
+      st.fallback = 1;
+      if (passes == 2) passes = 3;
+    }
+    launch_trsm_tall<T>(rows, l, Y, st.ld, st.Rcc.as<C>(), st.Dc.as<C>(), stream);
+  }
+  if (Rout) launch_upper_mult(l, st.R2.as<double>(), st.R1.as<double>(), Rout, lp, stream);
+}
+
+void ritz(SvdState& st, hipStream_t stream) {
+  const int l = st.l, lp = st.lp;
+  st.UR.ensure(static_cast<size_t>(l) * l * sizeof(double));
+  st.ZR.ensure(static_cast<size_t>(l) * l * sizeof(double));
+  st.sig.ensure(static_cast<size_t>(l) * sizeof(double));
+  st.jac_work.ensure(jacobi_workspace_doubles(l) * sizeof(double));
+  st.sweeps.ensure(sizeof(int));
+  launch_jacobi_svd(l, st.Rc.as<double>(), lp, st.UR.as<double>(), st.sig.as<double>(), st.ZR.as<double>(),
+                    st.jac_work.as<double>(), st.sweeps.as<int>(), stream);
+  st.have_ritz = true;
+}
+
+// rho of the current Ritz triplets, given Y = M Qc of the next iteration.
+template <typename T>
+double residual(SvdState& st, const T* Y, hipStream_t stream) {
+  using C = typename ComputeOf<T>::type;
+  const int l = st.l, k = st.k;
+  st.rhs.ensure(static_cast<size_t>(2) * l * k * sizeof(C));
+  st.left2.ensure(static_cast<size_t>(k) * sizeof(double));
+  st.right2.ensure(static_cast<size_t>(k) * sizeof(double));
+  st.cn_work.ensure(gemm_colnorm_workspace(st.r, k) * sizeof(double));
+  launch_pack_residual_rhs<C>(l, k, st.UR.as<double>(), st.ZR.as<double>(), st.sig.as<double>(), l,
+                              st.rhs.as<C>(), stream);
+  launch_gemm_tall<T>(st.r, k, l, Y, st.ld, l, st.qr.as<T>(), st.ld, st.rhs.as<C>(), k, nullptr, 0, 1.0, 0.0,
+                      GemmEpi::ColNorm2, st.left2.as<double>(), st.cn_work.as<double>(), stream);
+  launch_small_residual(l, k, st.Rc.as<double>(), st.lp, st.ZR.as<double>(), st.UR.as<double>(), l,
+                        st.sig.as<double>(), st.right2.as<double>(), stream);
+  std::vector<double> a(k), b(k), s(k);
+  ISVD_HIP(hipMemcpyAsync(a.data(), st.left2.p, k * sizeof(double), hipMemcpyDeviceToHost, stream));
+  ISVD_HIP(hipMemcpyAsync(b.data(), st.right2.p, k * sizeof(double), hipMemcpyDeviceToHost, stream));
+  ISVD_HIP(hipMemcpyAsync(s.data(), st.sig.p, k * sizeof(double), hipMemcpyDeviceToHost, stream));
+  ISVD_HIP(hipStreamSynchronize(stream));
+  double rho = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double v = s[i] > 0.0 ? std::sqrt(a[i] + b[i]) / s[i] : INFINITY;
+    rho = v > rho ? v : rho;
+  }
+  st.checks++;
+  return rho;
+}
+
+// U = Qr Z_R[:, :k], V = Qc U_R[:, :k] (outputs of type O), S = sig[:k].
+template <typename T, typename O>
+void finalize(SvdState& st, isvd_operator* op, void* U, int64_t ldu, double* S, void* V, int64_t ldv,
+              hipStream_t stream) {
+  using C = typename ComputeOf<T>::type;
+  using CO = typename ComputeOf<O>::type;
+  const int l = st.l, k = st.k;
+  DevBuf zb, ub, uo, vo;
+  zb.ensure(static_cast<size_t>(l) * k * sizeof(C));
+  ub.ensure(static_cast<size_t>(l) * k * sizeof(C));
+  launch_convert<C, double>(l, k, st.ZR.as<double>(), l, zb.as<C>(), k, stream);
+  launch_convert<C, double>(l, k, st.UR.as<double>(), l, ub.as<C>(), k, stream);
+  if constexpr (std::is_same<T, O>::value) {
+    launch_gemm_tall<T>(st.r, k, l, st.qr.as<T>(), st.ld, 0, nullptr, 0, zb.as<C>(), k, static_cast<T*>(U), ldu,
+                        1.0, 0.0, GemmEpi::Store, nullptr, nullptr, stream);
+    launch_gemm_tall<T>(st.c, k, l, st.qc.as<T>(), st.ld, 0, nullptr, 0, ub.as<C>(), k, static_cast<T*>(V), ldv,
+                        1.0, 0.0, GemmEpi::Store, nullptr, nullptr, stream);
+  } else {
+    // BF16 blocks, float outputs: widen the blocks first (exact), then multiply in FP32.
+    static_assert(std::is_same<CO, float>::value, "widening only to float");
+    DevBuf wide;
+    const int64_t rows = st.r > st.c ? st.r : st.c;
+    wide.ensure(static_cast<size_t>(rows) * st.ld * sizeof(float));
+    launch_convert<float, T>(st.r, l, st.qr.as<T>(), st.ld, wide.as<float>(), st.ld, stream);
+    launch_gemm_tall<float>(st.r, k, l, wide.as<float>(), st.ld, 0, nullptr, 0, zb.as<float>(), k,
+                            static_cast<float*>(U), ldu, 1.0, 0.0, GemmEpi::Store, nullptr, nullptr, stream);
+    launch_convert<float, T>(st.c, l, st.qc.as<T>(), st.ld, wide.as<float>(), st.ld, stream);
+    launch_gemm_tall<float>(st.c, k, l, wide.as<float>(), st.ld, 0, nullptr, 0, ub.as<float>(), k,
+                            static_cast<float*>(V), ldv, 1.0, 0.0, GemmEpi::Store, nullptr, nullptr, stream);
+    ISVD_HIP(hipStreamSynchronize(stream));
+  }
+  ISVD_HIP(hipMemcpyAsync(S, st.sig.p, k * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  ISVD_HIP(hipStreamSynchronize(stream));
+  (void)op;
+}
+
+template <typename T>
+void ensure_blocks(SvdState& st) {
+  st.qc.ensure(static_cast<size_t>(st.c) * st.ld * sizeof(T));
+  st.w.ensure(static_cast<size_t>(st.c) * st.ld * sizeof(T));
+  st.qr.ensure(static_cast<size_t>(st.r) * st.ld * sizeof(T));
+  st.y.ensure(static_cast<size_t>(st.r) * st.ld * sizeof(T));
+  st.Rc.ensure(static_cast<size_t>(st.lp) * st.lp * sizeof(double));
+}
+
+// Runs iterations in storage type T from the current Qc.  Returns 1 when the
+// Ritz triplets held in st satisfy the stopping rule of this phase (tolerance
+// `tol`, or the fixed count), 0 when max_iter was reached.
+template <typename T>
+int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, double tol, bool fixed, int t0,
+              hipStream_t stream) {
+  const int l = st.l;
+  const int every = prm->check_every > 0 ? prm->check_every : 1;
+  for (int t = t0;; ++t) {
+    T* Y = st.y.as<T>();
+    apply_operator<T>(op, false, st.qc.as<T>(), st.ld, l, Y, st.ld, stream);
+    st.applies++;
+    if (!fixed && st.have_ritz && st.ritz_iter == t - 1) {
+      st.residual = residual<T>(st, Y, stream);
+      if (st.residual <= tol) {
+        st.iterations = t - 1;
+        return 1;
+      }
+    }
+    if (!fixed && t >= prm->max_iter) {
+      // out of iterations: return the triplets of the last finished iteration
+      if (st.ritz_iter != t - 1 && t >= 1) {
+        ritz(st, stream);
+        st.ritz_iter = t - 1;
+      }
+      st.iterations = t - 1;
+      return 0;
+    }
+    orthonormalize<T>(st, Y, st.r, nullptr, stream);
+    std::swap(st.qr.p, st.y.p);
+    std::swap(st.qr.bytes, st.y.bytes);
+    apply_operator<T>(op, true, st.qr.as<T>(), st.ld, l, st.w.as<T>(), st.ld, stream);
+    st.applies++;
+    orthonormalize<T>(st, st.w.as<T>(), st.c, st.Rc.as<double>(), stream);
+    std::swap(st.qc.p, st.w.p);
+    std::swap(st.qc.bytes, st.w.bytes);
+    if (fixed && t >= prm->q) {
+      ritz(st, stream);
+      st.ritz_iter = t;
+      st.iterations = t;
+      return 1;
+    }
+    if (!fixed && (t % every == 0)) {
+      ritz(st, stream);
+      st.ritz_iter = t;
+    }
+  }
+}
+
+template <typename T>
+void load_start_block(SvdState& st, const isvd_svd_params* prm, hipStream_t stream) {
+  if (prm->omega) {
+    launch_convert<T, T>(st.c, st.l, static_cast<const T*>(prm->omega), prm->ld_omega, st.qc.as<T>(), st.ld, stream);
+  } else {
+    launch_gaussian<T>(st.c, st.l, prm->seed, st.qc.as<T>(), st.ld, stream);
+  }
+}
+
+template <typename T>
+isvd_status svd_same_precision(isvd_operator* op, const isvd_svd_params* prm, void* U, int64_t ldu, double* S,
+                               void* V, int64_t ldv, SvdState& st, hipStream_t stream) {
+  ensure_blocks<T>(st);
+  load_start_block<T>(st, prm, stream);
+  const bool fixed = !(prm->tol > 0.0);
+  const int ok = run_phase<T>(st, op, prm, prm->tol, fixed, 0, stream);
+  finalize<T, T>(st, op, U, ldu, S, V, ldv, stream);
+  return ok ? ISVD_OK : ISVD_E_NOT_CONVERGED;
+}
+
+isvd_status svd_bf16(isvd_operator* op, const isvd_svd_params* prm, void* U, int64_t ldu, double* S, void* V,
+                     int64_t ldv, SvdState& st, hipStream_t stream) {
+  ensure_blocks<bf16>(st);
+  load_start_block<bf16>(st, prm, stream);
+  const bool fixed = !(prm->tol > 0.0);
+  if (fixed || !(prm->fp32_switch_tol > 0.0)) {
+    const int ok = run_phase<bf16>(st, op, prm, prm->tol, fixed, 0, stream);
+    st.bf16_iterations = st.iterations + 1;
+    finalize<bf16, float>(st, op, U, ldu, S, V, ldv, stream);
+    return ok ? ISVD_OK : ISVD_E_NOT_CONVERGED;
+  }
+  // BF16 until rho <= fp32_switch_tol, then widen Qc and continue in FP32.
+  const int ok16 = run_phase<bf16>(st, op, prm, prm->fp32_switch_tol, false, 0, stream);
+  if (!ok16) {
+    st.bf16_iterations = st.iterations + 1;
+    finalize<bf16, float>(st, op, U, ldu, S, V, ldv, stream);
+    return ISVD_E_NOT_CONVERGED;
+  }
+  const int t_switch = st.iterations + 1;
+  st.bf16_iterations = t_switch;
+  // The BF16 phase stopped with Qc of iteration t_switch - 1 and one extra product;
+  // restart the FP32 phase from that Qc.
+  DevBuf qc32;
+  qc32.ensure(static_cast<size_t>(st.c) * st.ld * sizeof(float));
+  launch_convert<float, bf16>(st.c, st.l, st.qc.as<bf16>(), st.ld, qc32.as<float>(), st.ld, stream);
+  ISVD_HIP(hipStreamSynchronize(stream));
+  st.qc.release();
+  st.w.release();
+  st.qr.release();
+  st.y.release();
+  std::swap(st.qc.p, qc32.p);
+  std::swap(st.qc.bytes, qc32.bytes);
+  st.w.ensure(static_cast<size_t>(st.c) * st.ld * sizeof(float));
+  st.qr.ensure(static_cast<size_t>(st.r) * st.ld * sizeof(float));
+  st.y.ensure(static_cast<size_t>(st.r) * st.ld * sizeof(float));
+  st.have_ritz = false;
+  st.ritz_iter = -1;
+  const int ok = run_phase<float>(st, op, prm, prm->tol, false, t_switch, stream);
+  finalize<float, float>(st, op, U, ldu, S, V, ldv, stream);
+  return ok ? ISVD_OK : ISVD_E_NOT_CONVERGED;
+}
+
+}  // namespace
+
+isvd_status truncated_svd(isvd_operator* op, const isvd_svd_params* prm, void* U, int64_t ldu, double* S,
+                          void* V, int64_t ldv, isvd_svd_info* info, hipStream_t stream) {
+  const auto t_start = std::chrono::steady_clock::now();
+  ISVD_CHECK(op && prm && U && S && V, ISVD_E_INVALID, "null argument");
+  SvdState st;
+  st.r = op->rows;
+  st.c = op->cols;
+  st.k = prm->k;
+  st.l = prm->k + prm->p;
+  const int64_t mn = st.r < st.c ? st.r : st.c;
+  ISVD_CHECK(prm->k >= 1 && prm->p >= 0 && st.l <= mn, ISVD_E_INVALID, "need 1 <= k, 0 <= p, k + p <= min(rows, cols)");
+  ISVD_CHECK(st.l <= 512, ISVD_E_INVALID, "k + p above 512");
+  ISVD_CHECK(prm->q >= 0, ISVD_E_INVALID, "q must be >= 0");
+  ISVD_CHECK(!(prm->tol > 0.0) || prm->max_iter >= 1, ISVD_E_INVALID, "tolerance mode needs max_iter >= 1");
+  ISVD_CHECK(ldu >= st.k && ldv >= st.k, ISVD_E_INVALID, "ldu/ldv smaller than k");
+  ISVD_CHECK(!prm->omega || prm->ld_omega >= st.l, ISVD_E_INVALID, "ld_omega smaller than k + p");
+  st.lp = pad16(st.l);
+  st.ld = round_up(st.l, 8);
+  isvd_status rc;
+  switch (op->prec) {
+    case ISVD_FP64: rc = svd_same_precision<double>(op, prm, U, ldu, S, V, ldv, st, stream); break;
+    case ISVD_FP32: rc = svd_same_precision<float>(op, prm, U, ldu, S, V, ldv, st, stream); break;
+    default: rc = svd_bf16(op, prm, U, ldu, S, V, ldv, st, stream); break;
+  }
+  if (info) {
+    info->iterations = st.iterations;
+    info->applies = st.applies;
+    info->bf16_iterations = op->prec == ISVD_BF16 ? st.bf16_iterations : 0;
+    info->residual_checks = st.checks;
+    info->used_fallback = st.fallback;
+    info->residual = st.residual;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  if (rc == ISVD_E_NOT_CONVERGED) set_last_error("tolerance not reached within max_iter iterations");
+  return rc;
+}
+
+// Standalone CholeskyQR2 of one block.
+template <typename T>
+void orthonormalize_block(int64_t rows, int cols, T* Y, int64_t ld, double* Rout, hipStream_t stream) {
+  SvdState st;
+  st.l = cols;
+  st.lp = pad16(cols);
+  st.ld = ld;
+  st.Rc.ensure(static_cast<size_t>(st.lp) * st.lp * sizeof(double));
+  orthonormalize<T>(st, Y, rows, st.Rc.as<double>(), stream);
+  if (Rout) {
+    launch_convert<double, double>(cols, cols, st.Rc.as<double>(), st.lp, Rout, cols, stream);
+  }
+  ISVD_HIP(hipStreamSynchronize(stream));
+}
+template void orthonormalize_block<double>(int64_t, int, double*, int64_t, double*, hipStream_t);
+template void orthonormalize_block<float>(int64_t, int, float*, int64_t, double*, hipStream_t);
+template void orthonormalize_block<bf16>(int64_t, int, bf16*, int64_t, double*, hipStream_t);
+
+}  // namespace isvd

@@ -1,0 +1,360 @@
+// Fused CSR x tall-skinny pass (see spmm.h) and FP64 column sums.
+//
+// Light rows: a group of G lanes (G in {8, 16, 32, 64}) owns one output row
+// and all its columns; each lane holds NV 16-byte chunks of the row (or NV
+// single elements when the block is not 16-byte aligned).  The group
+// prefetches up to G column indices with one coalesced load, then
+// broadcasts them lane to lane and keeps U independent row gathers in
+// flight.  Rows longer than heavy_threshold ("hubs" of power-law graphs)
+// are taken by whole workgroups: four waves stride over the row's
+// nonzeros and combine their partial rows through LDS in a fixed order.
+#include "spmm.h"
+
+namespace isvd {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kUnroll = 4;
+
+// 16-byte chunk (VEC) or single-element access to a storage row.
+template <typename T, typename C, bool VEC> struct Chunk;
+
+template <typename T, typename C> struct Chunk<T, C, false> {
+  static constexpr int N = 1;
+  __device__ static inline void load(const T* p, C (&x)[N]) { x[0] = static_cast<C>(Elem<T>::load(p)); }
+  __device__ static inline void store(T* p, const C (&x)[N], int valid) {
+    if (valid > 0) Elem<T>::store(p, x[0]);
+  }
+};
+
+template <> struct Chunk<float, float, true> {
+  static constexpr int N = 4;
+  __device__ static inline void load(const float* p, float (&x)[N]) {
+    float4 v = *reinterpret_cast<const float4*>(p);
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+  }
+  __device__ static inline void store(float* p, const float (&x)[N], int valid) {
+    if (valid >= N) {
+      *reinterpret_cast<float4*>(p) = make_float4(x[0], x[1], x[2], x[3]);
+    } else {
+      for (int t = 0; t < valid; ++t) p[t] = x[t];
+    }
+  }
+};
+
+template <> struct Chunk<double, double, true> {
+  static constexpr int N = 2;
+  __device__ static inline void load(const double* p, double (&x)[N]) {
+    double2 v = *reinterpret_cast<const double2*>(p);
+    x[0] = v.x; x[1] = v.y;
+  }
+  __device__ static inline void store(double* p, const double (&x)[N], int valid) {
+    if (valid >= N) {
+      *reinterpret_cast<double2*>(p) = make_double2(x[0], x[1]);
+    } else if (valid > 0) {
+      p[0] = x[0];
+    }
+  }
+};
+
+template <> struct Chunk<bf16, float, true> {
+  static constexpr int N = 8;
+  __device__ static inline void load(const bf16* p, float (&x)[N]) {
+    uint4 v = *reinterpret_cast<const uint4*>(p);
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      x[2 * t] = bf16_to_float(static_cast<uint16_t>(w[t] & 0xffffu));
+      x[2 * t + 1] = bf16_to_float(static_cast<uint16_t>(w[t] >> 16));
+    }
+  }
+  __device__ static inline void store(bf16* p, const float (&x)[N], int valid) {
+    if (valid >= N) {
+      uint32_t w[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        w[t] = static_cast<uint32_t>(float_to_bf16(x[2 * t])) |
+               (static_cast<uint32_t>(float_to_bf16(x[2 * t + 1])) << 16);
+      *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+    } else {
+      for (int t = 0; t < valid; ++t) p[t].bits = float_to_bf16(x[t]);
+    }
+  }
+};
+
+template <int G>
+__device__ inline int bcast_i(int v, int src) {
+  if constexpr (G == 64) return __builtin_amdgcn_readlane(v, src);
+  else return __shfl(v, src, 64);
+}
+template <int G>
+__device__ inline float bcast_f(float v, int src) {
+  if constexpr (G == 64) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+  else return __shfl(v, src, 64);
+}
+template <int G>
+__device__ inline double bcast_f(double v, int src) {
+  if constexpr (G == 64) {
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffll), src);
+    int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), src);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+  } else {
+    return __shfl(v, src, 64);
+  }
+}
+
+// acc += sum over nonzeros base, base+step, ... (batches of G) of g * Src row.
+// gl: lane within group, gbase: first lane of the group, lanes own chunks gl + G*m.
+template <typename T, typename C, int G, int NV, bool VEC>
+__device__ inline void accumulate(const SpmmPass& p, int64_t beg, int64_t end, int64_t step, int gl,
+                                  int gbase, int nchunks, C (&acc)[NV][Chunk<T, C, VEC>::N]) {
+  using CK = Chunk<T, C, VEC>;
+  constexpr int EPC = CK::N;
+  const T* src = static_cast<const T*>(p.src);
+  const int64_t lds = p.ld_src;
+  const C* cscale = static_cast<const C*>(p.colscale);
+  const C csa = static_cast<C>(p.cs_a), csb = static_cast<C>(p.cs_b);
+  bool own[NV];
+#pragma unroll
+  for (int m = 0; m < NV; ++m) own[m] = (gl + G * m) < nchunks;
+
+  for (int64_t base = beg; base < end; base += step) {
+    const int cnt = static_cast<int>((end - base) < G ? (end - base) : G);
+    int myj = 0;
+    C myg = C(0);
+    if (gl < cnt) {
+      myj = p.indices[base + gl];
+      myg = p.values ? static_cast<C>(p.values[base + gl]) : C(1);
+      if (cscale) myg *= csa * cscale[myj] + csb;
+    }
+    int e = 0;
+    for (; e + kUnroll <= cnt; e += kUnroll) {
+      int j[kUnroll];
+      C g[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        j[u] = bcast_i<G>(myj, gbase + e + u);
+        g[u] = bcast_f<G>(myg, gbase + e + u);
+      }
+      C x[kUnroll][NV][EPC];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+          if (own[m]) CK::load(src + static_cast<int64_t>(j[u]) * lds + (gl + G * m) * EPC, x[u][m]);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+          if (own[m])
+#pragma unroll
+            for (int t = 0; t < EPC; ++t) acc[m][t] += g[u] * x[u][m][t];
+    }
+    for (; e < cnt; ++e) {
+      const int j = bcast_i<G>(myj, gbase + e);
+      const C g = bcast_f<G>(myg, gbase + e);
+#pragma unroll
+      for (int m = 0; m < NV; ++m) {
+        if (own[m]) {
+          C x[EPC];
+          CK::load(src + static_cast<int64_t>(j) * lds + (gl + G * m) * EPC, x);
+#pragma unroll
+          for (int t = 0; t < EPC; ++t) acc[m][t] += g * x[t];
+        }
+      }
+    }
+  }
+}
+
+template <typename T, typename C, int NV, bool VEC>
+__device__ inline void epilogue(const SpmmPass& p, int64_t row, int gl, int G, int nchunks,
+                                const C (&acc)[NV][Chunk<T, C, VEC>::N]) {
+  using CK = Chunk<T, C, VEC>;
+  constexpr int EPC = CK::N;
+  const C r = p.rowscale ? static_cast<const C*>(p.rowscale)[row] : C(0);
+  const C ka = static_cast<C>(p.a0) + static_cast<C>(p.a1) * r;
+  const C kb = static_cast<C>(p.b0) + static_cast<C>(p.b1) * r;
+  const C kc = static_cast<C>(p.c0) + static_cast<C>(p.c1) * r;
+  const C ke = static_cast<C>(p.e);
+  const T* add = static_cast<const T*>(p.add);
+  T* out = static_cast<T*>(p.out);
+  T* out2 = static_cast<T*>(p.out2);
+#pragma unroll
+  for (int m = 0; m < NV; ++m) {
+    const int ch = gl + G * m;
+    if (ch >= nchunks) continue;
+    const int col0 = ch * EPC;
+    const int valid = (p.ncols - col0) < EPC ? (p.ncols - col0) : EPC;
+    C y[EPC];
+#pragma unroll
+    for (int t = 0; t < EPC; ++t) y[t] = ka * acc[m][t];
+    if (add) {
+      C a[EPC];
+      CK::load(add + row * p.ld_add + col0, a);
+#pragma unroll
+      for (int t = 0; t < EPC; ++t) y[t] += kb * a[t];
+    }
+    if (p.svec) {
+#pragma unroll
+      for (int t = 0; t < EPC; ++t)
+        if (t < valid) y[t] += ke * static_cast<C>(p.svec[col0 + t]);
+    }
+    CK::store(out + row * p.ld_out + col0, y, valid);
+    if (out2) {
+      C z[EPC];
+#pragma unroll
+      for (int t = 0; t < EPC; ++t) z[t] = kc * acc[m][t];
+      CK::store(out2 + row * p.ld_out2 + col0, z, valid);
+    }
+  }
+}
+
+template <typename T, typename C, int G, int NV, bool VEC>
+__global__ __launch_bounds__(kThreads) void spmm_pass_kernel(SpmmPass p) {
+  using CK = Chunk<T, C, VEC>;
+  constexpr int EPC = CK::N;
+  __shared__ C red[kWaves][NV * EPC][64];
+  const int nchunks = (p.ncols + EPC - 1) / EPC;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  C acc[NV][EPC];
+#pragma unroll
+  for (int m = 0; m < NV; ++m)
+#pragma unroll
+    for (int t = 0; t < EPC; ++t) acc[m][t] = C(0);
+
+  if (static_cast<int64_t>(blockIdx.x) < p.n_heavy) {
+    // A hub row: the whole block.  Lanes own chunks lane + 64 m (NV covers
+    // nchunks for any G because G < 64 implies nchunks <= 32 and NV == 1).
+    const int64_t row = p.heavy_rows[blockIdx.x];
+    const int64_t beg = p.indptr[row], end = p.indptr[row + 1];
+    accumulate<T, C, 64, NV, VEC>(p, beg + 64 * wave, end, 64 * kWaves, lane, 0, nchunks, acc);
+#pragma unroll
+    for (int m = 0; m < NV; ++m)
+#pragma unroll
+      for (int t = 0; t < EPC; ++t) red[wave][m * EPC + t][lane] = acc[m][t];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int m = 0; m < NV; ++m)
+#pragma unroll
+        for (int t = 0; t < EPC; ++t) {
+          C s = red[0][m * EPC + t][lane];
+          for (int w = 1; w < kWaves; ++w) s += red[w][m * EPC + t][lane];
+          acc[m][t] = s;
+        }
+      epilogue<T, C, NV, VEC>(p, row, lane, 64, nchunks, acc);
+    }
+    return;
+  }
+
+  constexpr int kRowsPerWave = 64 / G;
+  const int64_t lb = static_cast<int64_t>(blockIdx.x) - p.n_heavy;
+  const int64_t row = (lb * kWaves + wave) * kRowsPerWave + lane / G;
+  if (row >= p.n_rows) return;
+  const int64_t beg = p.indptr[row], end = p.indptr[row + 1];
+  if (p.heavy_threshold > 0 && end - beg > p.heavy_threshold) return;
+  const int gl = lane % G;
+  const int gbase = lane - gl;
+  accumulate<T, C, G, NV, VEC>(p, beg, end, G, gl, gbase, nchunks, acc);
+  epilogue<T, C, NV, VEC>(p, row, gl, G, nchunks, acc);
+}
+
+template <typename T, typename C, int G, int NV, bool VEC>
+void launch_cfg(const SpmmPass& p, hipStream_t stream) {
+  constexpr int kRowsPerBlock = kWaves * (64 / G);
+  const int64_t light_blocks = ceil_div(p.n_rows, kRowsPerBlock);
+  const int64_t grid = p.n_heavy + light_blocks;
+  if (grid == 0) return;
+  hipLaunchKernelGGL((spmm_pass_kernel<T, C, G, NV, VEC>), dim3(static_cast<unsigned>(grid)),
+                     dim3(kThreads), 0, stream, p);
+  ISVD_LAUNCH_CHECK();
+}
+
+template <typename T, typename C, bool VEC>
+void launch_vec(const SpmmPass& p, hipStream_t stream) {
+  constexpr int EPC = Chunk<T, C, VEC>::N;
+  const int nchunks = static_cast<int>(ceil_div(p.ncols, EPC));
+  if (nchunks <= 8) return launch_cfg<T, C, 8, 1, VEC>(p, stream);
+  if (nchunks <= 16) return launch_cfg<T, C, 16, 1, VEC>(p, stream);
+  if (nchunks <= 32) return launch_cfg<T, C, 32, 1, VEC>(p, stream);
+  if (nchunks <= 64) return launch_cfg<T, C, 64, 1, VEC>(p, stream);
+  if (nchunks <= 128) return launch_cfg<T, C, 64, 2, VEC>(p, stream);
+  if (nchunks <= 192) return launch_cfg<T, C, 64, 3, VEC>(p, stream);
+  if (nchunks <= 256) return launch_cfg<T, C, 64, 4, VEC>(p, stream);
+  if (nchunks <= 512) return launch_cfg<T, C, 64, 8, VEC>(p, stream);
+  if (nchunks <= 1024) return launch_cfg<T, C, 64, 16, VEC>(p, stream);
+  throw Error{ISVD_E_INVALID, "spmm pass: more than 1024 columns"};
+}
+
+bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15u) == 0; }
+
+}  // namespace
+
+template <typename T>
+void launch_spmm_pass(const SpmmPass& p, hipStream_t stream) {
+  using C = typename ComputeOf<T>::type;
+  constexpr int EPC = 16 / sizeof(T);
+  ISVD_CHECK(p.ncols >= 1 && p.ncols <= 1024, ISVD_E_INVALID, "spmm pass: ncols out of range");
+  // 16-byte chunks only when every row of every block is whole chunks (no read past a row's end)
+  bool vec = p.ncols % EPC == 0 && aligned16(p.src) && aligned16(p.out) && p.ld_src % EPC == 0 &&
+             p.ld_out % EPC == 0;
+  if (p.add) vec = vec && aligned16(p.add) && p.ld_add % EPC == 0;
+  if (p.out2) vec = vec && aligned16(p.out2) && p.ld_out2 % EPC == 0;
+  if (vec) launch_vec<T, C, true>(p, stream);
+  else launch_vec<T, C, false>(p, stream);
+}
+
+template void launch_spmm_pass<double>(const SpmmPass&, hipStream_t);
+template void launch_spmm_pass<float>(const SpmmPass&, hipStream_t);
+template void launch_spmm_pass<bf16>(const SpmmPass&, hipStream_t);
+
+// ---------------------------------------------------------------- column sums
+
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void colsum_partial_kernel(int64_t rows, int cols, const T* y,
+                                                             int64_t ld, double* partial) {
+  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = per * blockIdx.x;
+  const int64_t r1 = r0 + per < rows ? r0 + per : rows;
+  for (int c0 = 0; c0 < cols; c0 += blockDim.x) {
+    const int c = c0 + threadIdx.x;
+    if (c >= cols) continue;
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) s += static_cast<double>(Elem<T>::load(y + r * ld + c));
+    partial[static_cast<int64_t>(blockIdx.x) * cols + c] = s;
+  }
+}
+
+__global__ void colsum_final_kernel(int nparts, int cols, const double* partial, double* s) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double acc = 0.0;
+  for (int b = 0; b < nparts; ++b) acc += partial[static_cast<int64_t>(b) * cols + c];
+  s[c] = acc;
+}
+
+}  // namespace
+
+template <typename T>
+void launch_colsum(int64_t rows, int cols, const T* y, int64_t ld, double* partial, double* s,
+                   hipStream_t stream) {
+  int nparts = static_cast<int>(rows < kColsumBlocks ? (rows > 0 ? rows : 1) : kColsumBlocks);
+  hipLaunchKernelGGL(colsum_partial_kernel<T>, dim3(nparts), dim3(256), 0, stream, rows, cols, y, ld,
+                     partial);
+  ISVD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(colsum_final_kernel, dim3(static_cast<unsigned>(ceil_div(cols, 256))), dim3(256),
+                     0, stream, nparts, cols, partial, s);
+  ISVD_LAUNCH_CHECK();
+}
+
+template void launch_colsum<double>(int64_t, int, const double*, int64_t, double*, double*, hipStream_t);
+template void launch_colsum<float>(int64_t, int, const float*, int64_t, double*, double*, hipStream_t);
+template void launch_colsum<bf16>(int64_t, int, const bf16*, int64_t, double*, double*, hipStream_t);
+
+}  // namespace isvd

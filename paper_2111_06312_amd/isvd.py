@@ -1,0 +1,252 @@
+"""ctypes binding of libisvd.so (argument marshalling only).
+
+Every function here forwards device pointers of torch tensors, sizes and
+the current HIP stream to the C ABI declared in include/isvd.h; all
+arithmetic runs in the library's HIP kernels.  The library must have been
+built (paper_2111_06312_amd/build.py); there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libisvd.so")
+_lib = None
+
+ISVD_OK, ISVD_E_INVALID, ISVD_E_OOM, ISVD_E_HIP, ISVD_E_NOT_SPD, ISVD_E_NOT_CONVERGED, ISVD_E_UNSUPPORTED = range(7)
+FP64, FP32, BF16 = 0, 1, 2
+FORM_NE, FORM_FEATPROP = 0, 1
+
+_DTYPE = {FP64: torch.float64, FP32: torch.float32, BF16: torch.bfloat16}
+_PREC = {torch.float64: FP64, torch.float32: FP32, torch.bfloat16: BF16}
+
+
+class IsvdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"isvd status {status}: {msg}")
+        self.status = status
+
+
+class _Graph(ct.Structure):
+    _fields_ = [("n", ct.c_int64), ("nnz", ct.c_int64), ("indptr", ct.c_void_p), ("indices", ct.c_void_p),
+                ("values", ct.c_void_p), ("symmetric", ct.c_int), ("t_indptr", ct.c_void_p),
+                ("t_indices", ct.c_void_p), ("t_values", ct.c_void_p), ("add_self_loops", ct.c_int)]
+
+
+class _Design(ct.Structure):
+    _fields_ = [("form", ct.c_int), ("K", ct.c_int), ("coeffs", ct.POINTER(ct.c_double)), ("lam", ct.c_double),
+                ("X", ct.c_void_p), ("d", ct.c_int64), ("ldx", ct.c_int64), ("L", ct.c_int)]
+
+
+class _SvdParams(ct.Structure):
+    _fields_ = [("k", ct.c_int), ("p", ct.c_int), ("q", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
+                ("check_every", ct.c_int), ("seed", ct.c_uint64), ("omega", ct.c_void_p),
+                ("ld_omega", ct.c_int64), ("fp32_switch_tol", ct.c_double)]
+
+
+class _SvdInfo(ct.Structure):
+    _fields_ = [("iterations", ct.c_int), ("applies", ct.c_int), ("bf16_iterations", ct.c_int),
+                ("residual_checks", ct.c_int), ("used_fallback", ct.c_int), ("residual", ct.c_double),
+                ("seconds", ct.c_double)]
+
+
+@dataclass
+class SvdInfo:
+    iterations: int
+    applies: int
+    bf16_iterations: int
+    residual_checks: int
+    used_fallback: int
+    residual: float
+    seconds: float
+    status: int = 0
+
+
+def load():
+    """Load libisvd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with paper_2111_06312_amd/build.py")
+    lib = ct.CDLL(_LIB_PATH)
+    vp, i64, st = ct.c_void_p, ct.c_int64, ct.c_int
+    lib.isvd_status_string.restype = ct.c_char_p
+    lib.isvd_last_error.restype = ct.c_char_p
+    lib.isvd_version.restype = ct.c_char_p
+    lib.isvd_create_operator.argtypes = [ct.POINTER(_Graph), ct.POINTER(_Design), st, vp, ct.POINTER(vp)]
+    lib.isvd_destroy_operator.argtypes = [vp]
+    lib.isvd_destroy_operator.restype = None
+    lib.isvd_operator_shape.argtypes = [vp, ct.POINTER(i64), ct.POINTER(i64)]
+    lib.isvd_matmul_block.argtypes = [vp, st, vp, i64, i64, vp, i64, vp]
+    lib.isvd_truncated_svd.argtypes = [vp, ct.POINTER(_SvdParams), vp, i64, vp, vp, i64, ct.POINTER(_SvdInfo), vp]
+    lib.isvd_gaussian_block.argtypes = [i64, i64, ct.c_uint64, st, vp, i64, vp]
+    lib.isvd_orthonormalize.argtypes = [i64, i64, st, vp, i64, vp, vp]
+    lib.isvd_gram.argtypes = [i64, i64, i64, st, vp, i64, vp, i64, vp, i64, vp]
+    lib.isvd_small_svd.argtypes = [i64, vp, vp, vp, vp, vp]
+    lib.isvd_ws_features.argtypes = [vp, vp, vp]
+    lib.isvd_ws_create.argtypes = [st, ct.c_uint64, ct.POINTER(vp)]
+    lib.isvd_ws_destroy.argtypes = [vp]
+    lib.isvd_ws_destroy.restype = None
+    lib.isvd_ws_num_params.argtypes = [vp]
+    lib.isvd_ws_num_params.restype = i64
+    lib.isvd_ws_get_params.argtypes = [vp, vp]
+    lib.isvd_ws_set_params.argtypes = [vp, vp]
+    lib.isvd_ws_forward.argtypes = [vp, i64, vp, vp, i64, vp]
+    lib.isvd_ws_train_step.argtypes = [vp, i64, vp, vp, i64, ct.c_double, ct.POINTER(ct.c_double), vp, vp]
+    lib.isvd_ws_omega.argtypes = [vp, vp, vp, st, ct.c_uint64, vp, i64, ct.POINTER(st), vp]
+    _lib = lib
+    return lib
+
+
+def _check(status, allow=()):
+    if status != ISVD_OK and status not in allow:
+        raise IsvdError(status, _lib.isvd_last_error().decode())
+    return status
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _ld(t):
+    assert t.dim() == 2 and t.stride(1) == 1, "blocks must be row-major with unit column stride"
+    return t.stride(0)
+
+
+class Operator:
+    """Implicit design matrix on the GPU (isvd_create_operator).
+
+    graph: synth.Graph (host arrays are copied to the device and kept alive).
+    form : "ne" (coeffs, lam, self_loops) or "featprop" (X torch tensor, L).
+    """
+
+    def __init__(self, graph, form="ne", coeffs=None, lam=0.0, self_loops=False, X=None, L=0,
+                 precision=FP32, device="cuda"):
+        lib = load()
+        self.precision = precision
+        self.dtype = _DTYPE[precision]
+        self.n = graph.n
+        self._indptr = torch.as_tensor(np.asarray(graph.indptr, dtype=np.int64), device=device)
+        self._indices = torch.as_tensor(np.asarray(graph.indices, dtype=np.int32), device=device)
+        if self._indices.numel() == 0:
+            self._indices = torch.zeros(1, dtype=torch.int32, device=device)
+        g = _Graph(n=graph.n, nnz=graph.nnz, indptr=self._indptr.data_ptr(), indices=self._indices.data_ptr(),
+                   values=None, symmetric=1, t_indptr=None, t_indices=None, t_values=None,
+                   add_self_loops=1 if self_loops else 0)
+        if form == "ne":
+            c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+            self._coeffs = c
+            dsn = _Design(form=FORM_NE, K=len(c), coeffs=c.ctypes.data_as(ct.POINTER(ct.c_double)),
+                          lam=float(lam), X=None, d=0, ldx=0, L=0)
+        elif form == "featprop":
+            assert X is not None and X.dtype == self.dtype and X.is_cuda
+            self._X = X
+            dsn = _Design(form=FORM_FEATPROP, K=0, coeffs=None, lam=0.0, X=X.data_ptr(), d=X.shape[1],
+                          ldx=_ld(X), L=int(L))
+        else:
+            raise ValueError(form)
+        handle = ct.c_void_p()
+        _check(lib.isvd_create_operator(ct.byref(g), ct.byref(dsn), precision, _stream(), ct.byref(handle)))
+        self.handle = handle
+        r, cc = ct.c_int64(), ct.c_int64()
+        _check(lib.isvd_operator_shape(handle, ct.byref(r), ct.byref(cc)))
+        self.shape = (r.value, cc.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.isvd_destroy_operator(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def matmul(self, Y, transpose=False, out=None):
+        """M @ Y (or M^T @ Y) through isvd_matmul_block; enqueued on the current stream."""
+        rows = self.shape[1] if transpose else self.shape[0]
+        if out is None:
+            out = torch.empty((rows, Y.shape[1]), dtype=self.dtype, device=Y.device)
+        assert Y.dtype == self.dtype and out.dtype == self.dtype
+        _check(_lib.isvd_matmul_block(self.handle, 1 if transpose else 0, _ptr(Y), _ld(Y), Y.shape[1],
+                                      _ptr(out), _ld(out), _stream()))
+        return out
+
+    def truncated_svd(self, k, p, q=2, tol=0.0, max_iter=1000, check_every=1, seed=0, omega=None,
+                      fp32_switch_tol=0.0, allow_not_converged=False):
+        """(U, S, V, info) through isvd_truncated_svd."""
+        r, c = self.shape
+        out_dtype = torch.float32 if self.precision == BF16 else self.dtype
+        dev = self._indptr.device
+        U = torch.empty((r, k), dtype=out_dtype, device=dev)
+        V = torch.empty((c, k), dtype=out_dtype, device=dev)
+        S = torch.empty(k, dtype=torch.float64, device=dev)
+        prm = _SvdParams(k=k, p=p, q=q, tol=tol, max_iter=max_iter, check_every=check_every, seed=seed,
+                         omega=_ptr(omega) if omega is not None else None,
+                         ld_omega=_ld(omega) if omega is not None else 0, fp32_switch_tol=fp32_switch_tol)
+        if omega is not None:
+            assert omega.dtype == self.dtype and omega.shape == (c, k + p)
+        info = _SvdInfo()
+        st = _check(_lib.isvd_truncated_svd(self.handle, ct.byref(prm), _ptr(U), k, _ptr(S), _ptr(V), k,
+                                            ct.byref(info), _stream()),
+                    allow=(ISVD_E_NOT_CONVERGED,) if allow_not_converged else ())
+        return U, S, V, SvdInfo(info.iterations, info.applies, info.bf16_iterations, info.residual_checks,
+                                info.used_fallback, info.residual, info.seconds, st)
+
+
+def gaussian_block(rows, cols, seed, dtype=torch.float32, device="cuda"):
+    load()
+    out = torch.empty((rows, cols), dtype=dtype, device=device)
+    _check(_lib.isvd_gaussian_block(rows, cols, seed, _PREC[dtype], _ptr(out), _ld(out), _stream()))
+    return out
+
+
+def orthonormalize(Y):
+    """In place CholeskyQR2 of Y; returns (Y, R) with R an FP64 tensor."""
+    load()
+    l = Y.shape[1]
+    R = torch.empty((l, l), dtype=torch.float64, device=Y.device)
+    _check(_lib.isvd_orthonormalize(Y.shape[0], l, _PREC[Y.dtype], _ptr(Y), _ld(Y), _ptr(R), _stream()))
+    return Y, R
+
+
+def gram(A, B=None):
+    """A^T B in FP64 (B defaults to A)."""
+    load()
+    B = A if B is None else B
+    C = torch.empty((A.shape[1], B.shape[1]), dtype=torch.float64, device=A.device)
+    _check(_lib.isvd_gram(A.shape[0], A.shape[1], B.shape[1], _PREC[A.dtype], _ptr(A), _ld(A), _ptr(B), _ld(B),
+                          _ptr(C), C.shape[1], _stream()))
+    return C
+
+
+def small_svd(A):
+    """(U, s, V) of a small square FP64 matrix by one-sided Jacobi."""
+    load()
+    n = A.shape[0]
+    A = A.contiguous()
+    U = torch.empty_like(A)
+    V = torch.empty_like(A)
+    s = torch.empty(n, dtype=torch.float64, device=A.device)
+    _check(_lib.isvd_small_svd(n, _ptr(A), _ptr(U), _ptr(s), _ptr(V), _stream()))
+    return U, s, V
+
+
+def exported_symbols_from_header(path=None):
+    """Names of the functions include/isvd.h declares (for the export test)."""
+    import re
+    path = path or os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "isvd.h")
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(isvd_[a-z0-9_]+)\s*\(", text)))

@@ -1,0 +1,52 @@
+"""Shared helpers of the GPU parity tests: build matching GPU / oracle operators
+from one seeded graph, and compare blocks."""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from oracle.operators import FeatPropDesignMatrix, NEDesignMatrix
+
+
+def to_dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def to_np(t):
+    return t.detach().float().cpu().numpy() if t.dtype == torch.bfloat16 else t.detach().cpu().numpy()
+
+
+def rounded(a, dtype):
+    """Host copy of `a` rounded to the device dtype, returned as float64."""
+    return torch.as_tensor(a).to(dtype).to(torch.float64).numpy()
+
+
+def ne_pair(lib, g, coeffs, lam, loops, precision):
+    gop = lib.Operator(g, form="ne", coeffs=coeffs, lam=lam, self_loops=loops, precision=precision)
+    oop = NEDesignMatrix.from_graph(g, coeffs, lam, add_self_loops=loops)
+    return gop, oop
+
+
+def featprop_pair(lib, g, x, L, precision):
+    dt = lib._DTYPE[precision]
+    xd = to_dev(x, dt)
+    gop = lib.Operator(g, form="featprop", X=xd, L=L, precision=precision)
+    oop = FeatPropDesignMatrix.from_graph(g, rounded(x, dt), L)
+    return gop, oop
+
+
+def col_rel_err(got, want):
+    """Max over columns of max|got - want| / max|want| (per column)."""
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    scale = np.maximum(np.abs(want).max(axis=0), 1e-300)
+    return float((np.abs(got - want).max(axis=0) / scale).max())
+
+
+def gapped_k(s_all, k, rel_gap=1e-3):
+    """Largest k' <= k whose Ritz gap (s_k' - s_k'+1)/s_k' is at least rel_gap."""
+    for kk in range(k, 0, -1):
+        if (s_all[kk - 1] - s_all[kk]) / s_all[kk - 1] >= rel_gap:
+            return kk
+    return 0

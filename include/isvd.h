@@ -214,6 +214,22 @@ isvd_status isvd_small_svd(int64_t n, const double* A, double* Uo, double* s, do
                            void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Measurement of the sparse passes (the kernel that bounds every product).
+ * ------------------------------------------------------------------------ */
+
+/* on != 0: from now on every sparse pass is bracketed by a hipEvent pair on
+ * its launch stream (adds one host sync per pass to read the CSR size); the
+ * record is cleared.  on == 0 stops recording. */
+isvd_status isvd_profile_spmm_enable(int on);
+
+/* Totals over the passes recorded since the last enable/read (host outputs):
+ * summed event durations in ms, algorithmic bytes counting every gathered row
+ * each time it is gathered (gather_bytes) and once per pass (compulsory_bytes),
+ * and the number of passes.  Waits for the recorded events; clears the record. */
+isvd_status isvd_profile_spmm_read(double* total_ms, double* gather_bytes, double* compulsory_bytes,
+                                   int64_t* launches);
+
+/* ---------------------------------------------------------------------------
  * Learned warm start (not in the paper): a 16 -> 128 -> 128 -> k MLP with
  * GELU maps per-node structural features to the first k columns of the
  * start block; the remaining p columns stay Gaussian.

@@ -197,4 +197,20 @@ isvd_status isvd_small_svd(int64_t n, const double* A, double* Uo, double* s, do
   });
 }
 
+isvd_status isvd_profile_spmm_enable(int on) {
+  return guarded([&]() -> isvd_status {
+    spmm_profile_enable(on != 0);
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_profile_spmm_read(double* total_ms, double* gather_bytes, double* compulsory_bytes,
+                                   int64_t* launches) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(total_ms && gather_bytes && compulsory_bytes && launches, ISVD_E_INVALID, "null argument");
+    spmm_profile_read(total_ms, gather_bytes, compulsory_bytes, launches);
+    return ISVD_OK;
+  });
+}
+
 }  // extern "C"

@@ -30,6 +30,12 @@ struct SvdState {
   double residual = -1.0;
   bool have_ritz = false;
   int ritz_iter = -1;
+  void reset_counters() {
+    iterations = applies = bf16_iterations = checks = fallback = 0;
+    residual = -1.0;
+    have_ritz = false;
+    ritz_iter = -1;
+  }
 };
 
 template <typename T>
@@ -285,7 +291,9 @@ isvd_status truncated_svd(isvd_operator* op, const isvd_svd_params* prm, void* U
                           void* V, int64_t ldv, isvd_svd_info* info, hipStream_t stream) {
   const auto t_start = std::chrono::steady_clock::now();
   ISVD_CHECK(op && prm && U && S && V, ISVD_E_INVALID, "null argument");
-  SvdState st;
+  if (!op->svd_cache) op->svd_cache = std::make_shared<SvdState>();
+  SvdState& st = *static_cast<SvdState*>(op->svd_cache.get());
+  st.reset_counters();
   st.r = op->rows;
   st.c = op->cols;
   st.k = prm->k;

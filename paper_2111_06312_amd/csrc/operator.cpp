@@ -37,6 +37,7 @@ template <typename T>
 SpmmPass base_pass(const isvd_operator* op, const Csr& csr, int ncols) {
   SpmmPass p;
   p.n_rows = op->n;
+  p.nnz = csr.nnz;
   p.indptr = csr.indptr;
   p.indices = csr.indices;
   p.values = csr.values;
@@ -204,10 +205,12 @@ void setup_csr(isvd_operator* op, Csr& csr, const int64_t* indptr, const int32_t
                bool loops, hipStream_t stream) {
   if (loops) {
     build_loop_csr(op->n, indptr, indices, values, op->nnz, csr.own_ptr, csr.own_idx, csr.own_val, stream);
+    csr.nnz = op->nnz + op->n;
     csr.indptr = csr.own_ptr.as<int64_t>();
     csr.indices = csr.own_idx.as<int32_t>();
     csr.values = values ? csr.own_val.as<float>() : nullptr;
   } else {
+    csr.nnz = op->nnz;
     csr.indptr = indptr;
     csr.indices = indices;
     csr.values = values;
@@ -272,6 +275,7 @@ void create_operator(const isvd_graph* g, const isvd_design* m, isvd_precision p
     op->bwd.indices = op->fwd.indices;
     op->bwd.values = op->fwd.values;
     op->bwd.n_heavy = op->fwd.n_heavy;
+    op->bwd.nnz = op->fwd.nnz;
     if (op->fwd.n_heavy > 0) {
       op->bwd.heavy.ensure(op->fwd.n_heavy * sizeof(int32_t));
       ISVD_HIP(hipMemcpyAsync(op->bwd.heavy.p, op->fwd.heavy.p, op->fwd.n_heavy * sizeof(int32_t),

@@ -2,6 +2,7 @@
 // drivers that evaluate M*Y and M^T*Y as sequences of fused sparse passes.
 #pragma once
 
+#include <memory>
 #include <vector>
 
 #include "common.h"
@@ -29,6 +30,7 @@ struct Csr {
   const int32_t* indices = nullptr;
   const float* values = nullptr;
   DevBuf own_ptr, own_idx, own_val, heavy;
+  int64_t nnz = 0;
   int64_t n_heavy = 0;
 };
 
@@ -54,6 +56,7 @@ struct isvd_operator {
   // workspace of the products
   isvd::DevBuf tmp[3];
   isvd::DevBuf colsum_part, svec, gram_work, side_c, side_b;
+  std::shared_ptr<void> svd_cache;  // workspace of isvd_truncated_svd, kept between calls
   hipStream_t stream = nullptr;
 
   template <typename T>

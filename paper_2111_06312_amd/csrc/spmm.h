@@ -16,6 +16,7 @@ namespace isvd {
 
 struct SpmmPass {
   int64_t n_rows = 0;
+  int64_t nnz = 0;  // stored entries (only used for byte accounting)
   const int64_t* indptr = nullptr;
   const int32_t* indices = nullptr;
   const float* values = nullptr;
@@ -43,6 +44,13 @@ struct SpmmPass {
   const int32_t* heavy_rows = nullptr;
   int64_t n_heavy = 0;
 };
+
+// Opt-in event timing of passes (profile.cpp).
+bool spmm_profiling();
+void* spmm_profile_begin(hipStream_t stream, double gather_bytes, double compulsory_bytes);
+void spmm_profile_end(hipStream_t stream, void* token);
+void spmm_profile_enable(bool on);
+void spmm_profile_read(double* ms, double* gather, double* compulsory, int64_t* launches);
 
 // Launch one pass; T = storage type (double, float, bf16).
 template <typename T>

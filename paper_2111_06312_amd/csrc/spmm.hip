@@ -304,8 +304,25 @@ void launch_spmm_pass(const SpmmPass& p, hipStream_t stream) {
              p.ld_out % EPC == 0;
   if (p.add) vec = vec && aligned16(p.add) && p.ld_add % EPC == 0;
   if (p.out2) vec = vec && aligned16(p.out2) && p.ld_out2 % EPC == 0;
+  void* tok = nullptr;
+  if (spmm_profiling()) {
+    // Algorithmic bytes of the pass: CSR arrays, gathered rows (every gather
+    // counted: "gather-inclusive"; each source row once: "compulsory"), the
+    // row-wise streams read and written.
+    const double n = static_cast<double>(p.n_rows), l = p.ncols, s = sizeof(T), cs = sizeof(C);
+    const double e = static_cast<double>(p.nnz);
+    double rows = n * l * s;                                   // out
+    if (p.add) rows += n * l * s;
+    if (p.out2) rows += n * l * s;
+    if (p.rowscale) rows += n * cs;
+    double csr = 8.0 * (n + 1) + 4.0 * e + (p.values ? 4.0 * e : 0.0);
+    const double gather = csr + rows + e * l * s + (p.colscale ? e * cs : 0.0);
+    const double compulsory = csr + rows + n * l * s + (p.colscale ? n * cs : 0.0);
+    tok = spmm_profile_begin(stream, gather, compulsory);
+  }
   if (vec) launch_vec<T, C, true>(p, stream);
   else launch_vec<T, C, false>(p, stream);
+  if (tok) spmm_profile_end(stream, tok);
 }
 
 template void launch_spmm_pass<double>(const SpmmPass&, hipStream_t);

@@ -100,6 +100,9 @@ def load():
     lib.isvd_ws_forward.argtypes = [vp, i64, vp, vp, i64, vp]
     lib.isvd_ws_train_step.argtypes = [vp, i64, vp, vp, i64, ct.c_double, ct.POINTER(ct.c_double), vp, vp]
     lib.isvd_ws_omega.argtypes = [vp, vp, vp, st, ct.c_uint64, vp, i64, ct.POINTER(st), vp]
+    lib.isvd_profile_spmm_enable.argtypes = [st]
+    lib.isvd_profile_spmm_read.argtypes = [ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
+                                           ct.POINTER(ct.c_double), ct.POINTER(i64)]
     _lib = lib
     return lib
 
@@ -203,6 +206,19 @@ class Operator:
                     allow=(ISVD_E_NOT_CONVERGED,) if allow_not_converged else ())
         return U, S, V, SvdInfo(info.iterations, info.applies, info.bf16_iterations, info.residual_checks,
                                 info.used_fallback, info.residual, info.seconds, st)
+
+
+def profile_spmm(on=True):
+    """Start (or stop) event timing of every sparse pass."""
+    load()
+    _check(_lib.isvd_profile_spmm_enable(1 if on else 0))
+
+
+def profile_spmm_read():
+    """(total_ms, gather_bytes, compulsory_bytes, launches) since profile_spmm()."""
+    ms, gb, cb, n = ct.c_double(), ct.c_double(), ct.c_double(), ct.c_int64()
+    _check(_lib.isvd_profile_spmm_read(ct.byref(ms), ct.byref(gb), ct.byref(cb), ct.byref(n)))
+    return ms.value, gb.value, cb.value, n.value
 
 
 def gaussian_block(rows, cols, seed, dtype=torch.float32, device="cuda"):

@@ -40,9 +40,12 @@ def parse():
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16"])
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2000)
-    ap.add_argument("--check-every", type=int, default=1)
+    ap.add_argument("--check-every", type=int, default=0)
     ap.add_argument("--fp32-switch-tol", type=float, default=1e-2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy a 1 GiB device buffer 3 times (a plain copy kernel of known size, "
+                         "to scale hardware byte counters)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "spmm_traffic.json"))
     return ap.parse_args()
 
@@ -92,6 +95,15 @@ def main():
     from synth.configs import make_graph
 
     lib.load()
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copies: 3 x 1 GiB device-to-device", file=sys.stderr, flush=True)
+        del src, dst
     cfg = CONFIGS[args.config]
     prec_name = args.precision or ("bf16" if cfg.precision == "bf16" else "fp32")
     precision = lib.BF16 if prec_name == "bf16" else lib.FP32
@@ -119,7 +131,8 @@ def main():
         times.append(time.perf_counter() - ts)
         infos.append(info)
         print(f"[bench] step {s}: {times[-1]:.3f} s, iterations {info.iterations}, applies {info.applies}, "
-              f"rho {info.residual:.2e}, status {info.status}", file=sys.stderr, flush=True)
+              f"rho {info.residual:.2e}, status {info.status}, ritz {info.ritz_steps}, sweeps {info.jacobi_sweeps}",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
     spmm_ms, gather_b, comp_b, launches = lib.profile_spmm_read()

@@ -137,7 +137,9 @@ isvd_status isvd_matmul_block(isvd_operator* op, int transpose, const void* Y, i
  *              per-triplet relative residual
  *                rho = max_i sqrt(|M v_i - s_i u_i|^2 + |M^T u_i - s_i v_i|^2) / s_i
  *              is <= tol, or max_iter iterations.
- *  check_every : tolerance mode checks rho every this many iterations (>= 1).
+ *  check_every : tolerance mode checks rho every this many iterations; 0 =
+ *              adaptive (checks placed where the observed geometric decay of rho
+ *              predicts the tolerance, at most 32 iterations apart).
  *  seed      : Philox seed for a device-drawn Gaussian start block when omega is NULL.
  *  omega     : optional device c x l start block (operator precision, leading
  *              dimension ld_omega), used verbatim.
@@ -165,6 +167,8 @@ typedef struct {
   int used_fallback;     /* 1 if a Cholesky breakdown was repaired by a shifted re-factorisation */
   double residual;       /* rho of the returned triplets (tolerance mode), else -1 */
   double seconds;        /* wall time of the call */
+  int ritz_steps;        /* small Rayleigh-Ritz SVDs computed */
+  int jacobi_sweeps;     /* Jacobi sweeps of the last of them */
 } isvd_svd_info;
 
 /* Rank-k truncated SVD of M (Algorithm 1, with CholeskyQR2 as the
@@ -202,8 +206,8 @@ isvd_status isvd_orthonormalize(int64_t rows, int64_t cols, isvd_precision preci
                                 int64_t ldy, double* R_out, void* stream);
 
 /* C = A^T B, A rows x m, B rows x p (same precision, leading dimensions lda,
- * ldb), C m x p FP64 row-major (ldc), products formed exactly and summed in
- * FP64 in a fixed order.  Enqueued only. */
+ * ldb, m + p <= 2048), C m x p FP64 row-major (ldc), products formed exactly
+ * and summed in FP64 in a fixed order.  Synchronises the stream. */
 isvd_status isvd_gram(int64_t rows, int64_t m, int64_t p, isvd_precision precision, const void* A,
                       int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc, void* stream);
 

@@ -158,8 +158,8 @@ isvd_status isvd_orthonormalize(int64_t rows, int64_t cols, isvd_precision preci
 isvd_status isvd_gram(int64_t rows, int64_t m, int64_t p, isvd_precision precision, const void* A, int64_t lda,
                       const void* B, int64_t ldb, double* C, int64_t ldc, void* stream) {
   return guarded([&]() -> isvd_status {
-    ISVD_CHECK(A && B && C && rows >= 0 && m >= 1 && p >= 1 && m <= 2048 && p <= 2048, ISVD_E_INVALID,
-               "bad gram arguments");
+    ISVD_CHECK(A && B && C && rows >= 0 && m >= 1 && p >= 1 && m + p <= 2048, ISVD_E_INVALID,
+               "bad gram arguments (need m + p <= 2048)");
     ISVD_CHECK(lda >= m && ldb >= p && ldc >= p, ISVD_E_INVALID, "leading dimension too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
     DevBuf work;

@@ -55,9 +55,13 @@ void launch_cholesky(int l, const double* G, int64_t ldg, double shift, double r
                      C* Rc, C* Dinv_c, int* flag, hipStream_t stream);
 
 // In place Y <- Y R^-1 (rows x l block, storage T, ld), R/Dinv from launch_cholesky.
+// colsum (optional, l doubles): FP64 column sums of the stored result, reduced
+// in a fixed order through `work` (trsm_colsum_workspace doubles).
 template <typename T>
 void launch_trsm_tall(int64_t rows, int l, T* Y, int64_t ld, const typename ComputeOf<T>::type* Rc,
-                      const typename ComputeOf<T>::type* Dinv, hipStream_t stream);
+                      const typename ComputeOf<T>::type* Dinv, double* colsum, double* work,
+                      hipStream_t stream);
+inline size_t trsm_colsum_workspace(int l) { return static_cast<size_t>(1024) * l; }
 
 // C = A * B for upper-triangular l x l FP64 matrices (padded lp, ld lp).
 void launch_upper_mult(int l, const double* A, const double* B, double* C, int64_t ld,

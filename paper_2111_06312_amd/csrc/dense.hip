@@ -31,9 +31,10 @@ __device__ inline C ld_as(const T* p) { return static_cast<C>(Elem<T>::load(p));
 
 // ============================================================ Gram
 
-constexpr int kGramWaves = 4;
-constexpr int kGramTPW = 8;  // tiles per wave
-constexpr int kGramTPB = kGramWaves * kGramTPW;
+constexpr int kGramWaves = 8;
+constexpr int kGramThreads = 64 * kGramWaves;
+constexpr int kGramMaxTPW = 24;      // tiles per wave of the largest instantiation
+constexpr int kGramPrefetch = 16;    // staged elements per thread per row chunk
 constexpr int kGramMaxParts = 256;
 
 __device__ inline void decode_tile(int idx, bool same, int tm, int tp, int& ti, int& tj) {
@@ -51,60 +52,76 @@ __device__ inline void decode_tile(int idx, bool same, int tm, int tp, int& ti, 
   }
 }
 
-template <typename TA, typename TB>
-__global__ __launch_bounds__(256) void gram_partial_kernel(int64_t rows, int m, int p, const TA* A,
-                                                           int64_t lda, const TB* B, int64_t ldb,
-                                                           int same, int tm, int tp, int ntiles,
-                                                           int64_t rows_per_block, int rb,
-                                                           double* partial, int mp, int pp) {
+// Partial A^T B over one row slice per blockIdx.x, for the 16 x 16 output tiles
+// of group blockIdx.y.  Row chunks of rb rows are staged in LDS as FP64; the
+// next chunk is loaded into registers while the MFMAs of the current one run.
+template <typename TA, typename TB, int TPW>
+__global__ __launch_bounds__(kGramThreads) void gram_partial_kernel(int64_t rows, int m, int p, const TA* A,
+                                                                    int64_t lda, const TB* B, int64_t ldb,
+                                                                    int same, int tm, int tp, int ntiles,
+                                                                    int tiles_per_group, int64_t rows_per_block,
+                                                                    int rb, double* partial, int mp, int pp) {
+  using PF = typename ComputeOf<TA>::type;
   extern __shared__ double gsm[];
   double* As = gsm;
   double* Bs = same ? gsm : gsm + rb * mp;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int ti[kGramTPW], tj[kGramTPW];
-  bool act[kGramTPW];
-  v4d acc[kGramTPW];
+  const int li = lane & 15, lk = lane >> 4;
+  const int gfirst = blockIdx.y * tiles_per_group;
+  const int glast = min(ntiles, gfirst + tiles_per_group);
+  int ti[TPW], tj[TPW];
+  bool act[TPW];
+  v4d acc[TPW];
 #pragma unroll
-  for (int t = 0; t < kGramTPW; ++t) {
-    const int idx = blockIdx.y * kGramTPB + wave + kGramWaves * t;
-    act[t] = idx < ntiles;
+  for (int t = 0; t < TPW; ++t) {
+    const int idx = gfirst + wave + kGramWaves * t;
+    act[t] = idx < glast;
     ti[t] = tj[t] = 0;
     if (act[t]) decode_tile(idx, same, tm, tp, ti[t], tj[t]);
     acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
   }
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
-  const int li = lane & 15, lk = lane >> 4;
+  const int na = rb * mp, nb = same ? 0 : rb * pp;
+  PF pf[kGramPrefetch];
+  auto fetch = [&](int64_t base) {
+#pragma unroll
+    for (int i = 0; i < kGramPrefetch; ++i) {
+      const int f = threadIdx.x + kGramThreads * i;
+      PF v = PF(0);
+      if (f < na) {
+        const int r = f / mp, c = f - r * mp;
+        const int64_t row = base + r;
+        if (row < r1 && c < m) v = static_cast<PF>(Elem<TA>::load(A + row * lda + c));
+      } else if (f < na + nb) {
+        const int g = f - na, r = g / pp, c = g - r * pp;
+        const int64_t row = base + r;
+        if (row < r1 && c < p) v = static_cast<PF>(Elem<TB>::load(B + row * ldb + c));
+      }
+      pf[i] = v;
+    }
+  };
+  if (r0 < r1) fetch(r0);
   for (int64_t base = r0; base < r1; base += rb) {
     __syncthreads();
-    for (int f = threadIdx.x; f < rb * mp; f += blockDim.x) {
-      const int r = f / mp, c = f - r * mp;
-      const int64_t row = base + r;
-      As[f] = (row < r1 && c < m) ? ld_as<double>(A + row * lda + c) : 0.0;
-    }
-    if (!same) {
-      for (int f = threadIdx.x; f < rb * pp; f += blockDim.x) {
-        const int r = f / pp, c = f - r * pp;
-        const int64_t row = base + r;
-        Bs[f] = (row < r1 && c < p) ? ld_as<double>(B + row * ldb + c) : 0.0;
-      }
+#pragma unroll
+    for (int i = 0; i < kGramPrefetch; ++i) {
+      const int f = threadIdx.x + kGramThreads * i;
+      if (f < na + nb) gsm[f] = static_cast<double>(pf[i]);
     }
     __syncthreads();
+    if (base + rb < r1) fetch(base + rb);
     for (int kk = 0; kk < rb / 4; ++kk) {
       const int kr = kk * 4 + lk;
 #pragma unroll
-      for (int t = 0; t < kGramTPW; ++t) {
-        if (act[t]) {
-          const double a = As[kr * mp + ti[t] * 16 + li];
-          const double b = Bs[kr * pp + tj[t] * 16 + li];
-          acc[t] = mfma4(a, b, acc[t]);
-        }
+      for (int t = 0; t < TPW; ++t) {
+        if (act[t]) acc[t] = mfma4(As[kr * mp + ti[t] * 16 + li], Bs[kr * pp + tj[t] * 16 + li], acc[t]);
       }
     }
   }
   double* part = partial + static_cast<int64_t>(blockIdx.x) * mp * pp;
 #pragma unroll
-  for (int t = 0; t < kGramTPW; ++t) {
+  for (int t = 0; t < TPW; ++t) {
     if (!act[t]) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -112,11 +129,15 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(int64_t rows, int m, 
   }
 }
 
-__global__ void gram_reduce_kernel(int m, int p, int nparts, const double* partial, int mp, int pp,
-                                   int same, double* C, int64_t ldc) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= static_cast<int64_t>(m) * p) return;
-  const int a = static_cast<int>(idx / p), b = static_cast<int>(idx % p);
+// C[a][b] = sum over row slices of the partial Gram tiles: 64 outputs per
+// block, four interleaved partial sums per output, combined in a fixed order.
+__global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int nparts, const double* partial, int mp,
+                                                          int pp, int same, double* C, int64_t ldc) {
+  __shared__ double red[4][64];
+  const int e = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 64 + e;
+  const bool ok = idx < static_cast<int64_t>(m) * p;
+  const int a = ok ? static_cast<int>(idx / p) : 0, b = ok ? static_cast<int>(idx % p) : 0;
   int sa = a, sb = b;
   if (same && (a >> 4) > (b >> 4)) {
     sa = b;
@@ -125,12 +146,15 @@ __global__ void gram_reduce_kernel(int m, int p, int nparts, const double* parti
   double s = 0.0;
   const int64_t stride = static_cast<int64_t>(mp) * pp;
   const int64_t off = static_cast<int64_t>(sa) * pp + sb;
-  for (int q = 0; q < nparts; ++q) s += partial[q * stride + off];
-  C[static_cast<int64_t>(a) * ldc + b] = s;
+  if (ok)
+    for (int q = w; q < nparts; q += 4) s += partial[q * stride + off];
+  red[w][e] = s;
+  __syncthreads();
+  if (w == 0 && ok) C[static_cast<int64_t>(a) * ldc + b] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
 }
 
 struct GramPlan {
-  int mp, pp, tm, tp, ntiles, rb, nparts, groups;
+  int mp, pp, tm, tp, ntiles, rb, nparts, groups, tpg, tpw;
   int64_t rows_per_block;
   size_t lds;
 };
@@ -143,26 +167,40 @@ GramPlan plan_gram(int64_t rows, int m, int p, bool same) {
   g.tp = g.pp / 16;
   g.ntiles = same ? g.tm * (g.tm + 1) / 2 : g.tm * g.tp;
   const int cols = g.mp + (same ? 0 : g.pp);
-  g.rb = 16;
-  while (g.rb > 4 && static_cast<size_t>(g.rb) * cols * 8 > 64 * 1024) g.rb /= 2;
+  g.rb = 32;
+  while (g.rb > 4 && (g.rb * cols > kGramThreads * kGramPrefetch ||
+                      static_cast<size_t>(g.rb) * cols * 8 > 96 * 1024))
+    g.rb /= 2;
+  ISVD_CHECK(g.rb * cols <= kGramThreads * kGramPrefetch, ISVD_E_INVALID, "gram: block too wide");
   g.lds = static_cast<size_t>(g.rb) * cols * 8;
+  g.groups = static_cast<int>(ceil_div(g.ntiles, kGramWaves * kGramMaxTPW));
+  g.tpg = static_cast<int>(ceil_div(g.ntiles, g.groups));
+  g.tpw = static_cast<int>(ceil_div(g.tpg, kGramWaves));
   const int64_t want = ceil_div(rows > 0 ? rows : 1, kGramMaxParts);
-  g.rows_per_block = round_up(want < 64 ? 64 : want, g.rb);
+  g.rows_per_block = round_up(want < 64 ? 64 : want, 32);
   g.nparts = static_cast<int>(ceil_div(rows > 0 ? rows : 1, g.rows_per_block));
-  g.groups = static_cast<int>(ceil_div(g.ntiles, kGramTPB));
   return g;
+}
+
+template <typename TA, typename TB, int TPW>
+void gram_launch(const GramPlan& g, int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
+                 bool same, double* work, hipStream_t stream) {
+  hipLaunchKernelGGL((gram_partial_kernel<TA, TB, TPW>), dim3(g.nparts, g.groups), dim3(kGramThreads), g.lds,
+                     stream, rows, m, p, A, lda, B, ldb, same ? 1 : 0, g.tm, g.tp, g.ntiles, g.tpg,
+                     g.rows_per_block, g.rb, work, g.mp, g.pp);
+  ISVD_LAUNCH_CHECK();
 }
 
 template <typename TA, typename TB>
 void gram_impl(int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
                bool same, double* C, int64_t ldc, double* work, hipStream_t stream) {
   const GramPlan g = plan_gram(rows, m, p, same);
-  hipLaunchKernelGGL((gram_partial_kernel<TA, TB>), dim3(g.nparts, g.groups), dim3(256), g.lds,
-                     stream, rows, m, p, A, lda, B, ldb, same ? 1 : 0, g.tm, g.tp, g.ntiles,
-                     g.rows_per_block, g.rb, work, g.mp, g.pp);
-  ISVD_LAUNCH_CHECK();
+  if (g.tpw <= 4) gram_launch<TA, TB, 4>(g, rows, m, p, A, lda, B, ldb, same, work, stream);
+  else if (g.tpw <= 8) gram_launch<TA, TB, 8>(g, rows, m, p, A, lda, B, ldb, same, work, stream);
+  else if (g.tpw <= 12) gram_launch<TA, TB, 12>(g, rows, m, p, A, lda, B, ldb, same, work, stream);
+  else gram_launch<TA, TB, kGramMaxTPW>(g, rows, m, p, A, lda, B, ldb, same, work, stream);
   const int64_t total = static_cast<int64_t>(m) * p;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(total, 256))), dim3(256),
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(total, 64))), dim3(256),
                      0, stream, m, p, g.nparts, work, g.mp, g.pp, same ? 1 : 0, C, ldc);
   ISVD_LAUNCH_CHECK();
 }
@@ -274,6 +312,7 @@ __global__ __launch_bounds__(256) void colpart_reduce_kernel(int nparts, int N, 
 }
 
 constexpr int kColnormParts = 1024;
+constexpr int kTrsmParts = 1024;
 
 template <typename T, typename C, int TN>
 void gemm_launch_tn(int64_t M, int N, int K1, const T* A1, int64_t lda1, int K2, const T* A2,
@@ -299,80 +338,126 @@ void gemm_launch_tn(int64_t M, int N, int K1, const T* A1, int64_t lda1, int K2,
 
 // ============================================================ Cholesky
 
-// Factor one 16 x 16 diagonal tile in registers: lane c (0..15) holds column c.
-// On return s[k] = R[k][c] (upper, zero below the diagonal) and x[k] = (R^-1)[k][c].
-__device__ inline void tile_cholesky(double (&s)[16], double (&x)[16], int c, double refv,
-                                     double rel_tol, int* bad) {
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    double t = 0.0;
-#pragma unroll
-    for (int k = 0; k < j; ++k) t += __shfl(s[k], j, 64) * s[k];
-    const double v = s[j] - t;
-    const double piv = __shfl(v, j, 64);
-    const double ref = __shfl(refv, j, 64);
-    if (!(piv > rel_tol * ref) || !isfinite(piv)) *bad = 1;
-    const double rjj = sqrt(piv > 0.0 ? piv : 1e-300);
-    s[j] = (c > j) ? v / rjj : (c == j ? rjj : 0.0);
+// Orders LDS accesses of one wave: LDS operations of a wave execute in
+// program order, so a compiler barrier plus wave-scope fences suffice.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Working storage of the blocked factorisation: the upper tiles (I <= J) of an
+// lp x lp matrix, either packed in LDS (small l) or in a global lp x lp array.
+struct TileStore {
+  double* lds;   // packed upper tiles, 256 doubles each, or null
+  double* glob;  // lp x lp row-major
+  int T, lp;
+  __device__ inline double& at(int I, int J, int r, int c) const {
+    if (lds) return lds[(static_cast<int64_t>(I) * T - static_cast<int64_t>(I) * (I - 1) / 2 + (J - I)) * 256 + r * 16 + c];
+    return glob[static_cast<int64_t>(I * 16 + r) * lp + J * 16 + c];
   }
+};
+
+constexpr int kCholLdsMaxTiles = 11;   // 66 packed tiles = 132 KB of LDS
+constexpr int kJacobiMaxNForChol = 1024;  // l <= 1024
+
+// One wave factors diagonal tile J (right-looking, in the scratch tile `S`)
+// and inverts its upper factor column by column into `X`.
+__device__ inline void diag_tile(const TileStore& W, int J, double* S, double* X, const double* refd,
+                                 double rel_tol, int lane, int* bad) {
+  for (int e = lane; e < 256; e += 64) S[e] = W.at(J, J, e >> 4, e & 15);
+  wave_lds_sync();
+  for (int j = 0; j < 16; ++j) {
+    const double ref = refd[J * 16 + j];
+    const double piv = S[j * 16 + j];
+    if ((!(piv > rel_tol * ref) || !isfinite(piv)) && lane == 0) *bad = 1;
+    const double r = sqrt(piv > 0.0 ? piv : 1e-300);
+    const double rinv = 1.0 / r;
+    wave_lds_sync();
+    if (lane > j && lane < 16) S[j * 16 + lane] *= rinv;
+    if (lane == j) S[j * 16 + j] = r;
+    wave_lds_sync();
+    // trailing update of the tile: S[a][b] -= R[j][a] R[j][b], j < a <= b
+    for (int e = lane; e < 256; e += 64) {
+      const int a = e >> 4, bb = e & 15;
+      if (a > j && bb >= a) S[e] -= S[j * 16 + a] * S[j * 16 + bb];
+    }
+    wave_lds_sync();
+  }
+  // X = R^-1: lane c solves R x = e_c by back substitution (x_i = 0 for i > c)
+  // reciprocals of the 16 pivots, one per lane, then back substitution by multiplication
+  if (lane < 16) X[lane * 16 + lane] = 1.0 / S[lane * 16 + lane];
+  wave_lds_sync();
+  if (lane < 16) {
+    const int c = lane;
+    double x[16];
 #pragma unroll
-  for (int i = 15; i >= 0; --i) {
-    double acc = (i == c) ? 1.0 : 0.0;
+    for (int i = 15; i >= 0; --i) {
+      double acc = (i == c) ? 1.0 : 0.0;
 #pragma unroll
-    for (int k = i + 1; k < 16; ++k) acc -= __shfl(s[i], k, 64) * x[k];
-    x[i] = acc / __shfl(s[i], i, 64);
+      for (int k = i + 1; k < 16; ++k) acc -= S[i * 16 + k] * x[k];
+      x[i] = (i <= c) ? acc * X[i * 16 + i] : 0.0;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) X[i * 16 + c] = x[i];
+  }
+  wave_lds_sync();
+  for (int e = lane; e < 256; e += 64) {
+    const int a = e >> 4, bb = e & 15;
+    W.at(J, J, a, bb) = (bb >= a) ? S[e] : 0.0;
   }
 }
 
 template <typename C>
 __global__ __launch_bounds__(1024) void cholesky_kernel(int l, const double* G, int64_t ldg, double shift,
-                                                        double rel_tol, double* W, C* Rc, C* Dc, int* flag) {
+                                                        double rel_tol, double* R64, C* Rc, C* Dc, int* flag) {
+  extern __shared__ double chol_lds[];
   const int lp = pad16(l), T = lp / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  __shared__ double dinv_s[256];
+  __shared__ double S[256], X[256];
+  __shared__ double refd[kJacobiMaxNForChol];
   __shared__ int bad;
-  for (int64_t idx = tid; idx < static_cast<int64_t>(lp) * lp; idx += blockDim.x) {
-    const int i = static_cast<int>(idx / lp), j = static_cast<int>(idx % lp);
+  TileStore W{T <= kCholLdsMaxTiles ? chol_lds : nullptr, R64, T, lp};
+  for (int i = tid; i < lp; i += blockDim.x)
+    refd[i] = i < l ? fabs(G[static_cast<int64_t>(i) * ldg + i] + shift) : 1.0;
+  // W = G + shift I on the upper tiles, identity on the padding
+  const int ntiles = T * (T + 1) / 2;
+  for (int64_t f = tid; f < static_cast<int64_t>(ntiles) * 256; f += blockDim.x) {
+    int I = 0, rem = static_cast<int>(f >> 8);
+    while (rem >= T - I) {
+      rem -= T - I;
+      ++I;
+    }
+    const int J = I + rem, r = (f >> 4) & 15, c = f & 15;
+    const int i = I * 16 + r, j = J * 16 + c;
     double v = (i == j) ? 1.0 : 0.0;
     if (i < l && j < l) v = G[static_cast<int64_t>(i) * ldg + j] + (i == j ? shift : 0.0);
-    W[idx] = v;
+    W.at(I, J, r, c) = v;
   }
   if (tid == 0) bad = 0;
   __syncthreads();
   for (int J = 0; J < T; ++J) {
-    const int o = J * 16;
     if (wave == 0) {
-      const int gi = o + li;
-      const double refv = gi < l ? fabs(G[static_cast<int64_t>(gi) * ldg + gi] + shift) : 1.0;
-      double s[16], x[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) s[k] = W[static_cast<int64_t>(o + k) * lp + o + li];
       int mybad = 0;
-      tile_cholesky(s, x, li, refv, rel_tol, &mybad);
+      diag_tile(W, J, S, X, refd, rel_tol, lane, &mybad);
       if (mybad && lane == 0) bad = 1;
-      if (lane < 16) {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          W[static_cast<int64_t>(o + k) * lp + o + li] = s[k];
-          dinv_s[k * 16 + li] = x[k];
-          Dc[J * 256 + k * 16 + li] = static_cast<C>(x[k]);
-        }
-      }
+      for (int e = lane; e < 256; e += 64) Dc[J * 256 + e] = static_cast<C>(X[e]);
     }
     __syncthreads();
-    // panel: R_JK = Dinv^T W_JK, K > J
+    // panel: R_JK = (R_JJ^-1)^T W_JK for K > J
     for (int K = J + 1 + wave; K < T; K += nw) {
       v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int kr = kk * 4 + lk;
-        const double a = dinv_s[kr * 16 + li];
-        const double b = W[static_cast<int64_t>(o + kr) * lp + K * 16 + li];
-        acc = mfma4(a, b, acc);
+        acc = mfma4(X[kr * 16 + li], W.at(J, K, kr, li), acc);
       }
+      // all lanes read their operands before any lane overwrites the tile
+      wave_lds_sync();
 #pragma unroll
-      for (int r = 0; r < 4; ++r) W[static_cast<int64_t>(o + drow<double>(lk, r)) * lp + K * 16 + li] = acc[r];
+      for (int r = 0; r < 4; ++r) W.at(J, K, drow<double>(lk, r), li) = acc[r];
     }
     __syncthreads();
     // trailing update: W_KK' -= R_JK^T R_JK', J < K <= K'
@@ -387,26 +472,24 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(int l, const double* G, 
       const int K = J + 1 + a_, K2 = K + q;
       v4d acc;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = W[static_cast<int64_t>(K * 16 + drow<double>(lk, r)) * lp + K2 * 16 + li];
+      for (int r = 0; r < 4; ++r) acc[r] = W.at(K, K2, drow<double>(lk, r), li);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int kr = kk * 4 + lk;
-        const double a = W[static_cast<int64_t>(o + kr) * lp + K * 16 + li];
-        const double b = W[static_cast<int64_t>(o + kr) * lp + K2 * 16 + li];
-        acc = mfma4(-a, b, acc);
+        acc = mfma4(-W.at(J, K, kr, li), W.at(J, K2, kr, li), acc);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) W[static_cast<int64_t>(K * 16 + drow<double>(lk, r)) * lp + K2 * 16 + li] = acc[r];
+      for (int r = 0; r < 4; ++r) W.at(K, K2, drow<double>(lk, r), li) = acc[r];
     }
     __syncthreads();
   }
+  // R64 and Rc: upper tiles of W, zeros below the diagonal
   for (int64_t idx = tid; idx < static_cast<int64_t>(lp) * lp; idx += blockDim.x) {
     const int i = static_cast<int>(idx / lp), j = static_cast<int>(idx % lp);
-    double v = W[idx];
-    if (i > j) {
-      v = 0.0;
-      W[idx] = 0.0;
-    }
+    const int I = i >> 4, J = j >> 4;
+    const double v = (I <= J && (I < J || (i & 15) <= (j & 15))) ? W.at(I, J, i & 15, j & 15) : 0.0;
+    if (W.lds) R64[idx] = v;
+    else if (I > J) R64[idx] = 0.0;
     Rc[idx] = static_cast<C>(v);
   }
   if (tid == 0) *flag = bad;
@@ -414,49 +497,86 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(int l, const double* G, 
 
 // ============================================================ tall triangular solve
 
+// Each wave owns 16 rows of a 16*nwave-row block; column tile K of Q needs
+// R[0..K][K] (a 16-column strip of R) and the inverse of R's diagonal tile K,
+// staged once per block in LDS and shared by its waves.  Blocks stride over
+// the row blocks.  With colpart, each block also writes the FP64 column sums
+// of the Q rows it produced (values as stored) to colpart[blockIdx.x][:].
 template <typename T, typename C>
-__global__ void trsm_tall_kernel(int64_t rows, int l, T* Y, int64_t ld, const C* Rc, const C* Dc) {
+__global__ void trsm_tall_kernel(int64_t rows, int l, T* Y, int64_t ld, const C* Rc, const C* Dc,
+                                 double* colpart) {
   using V = typename Acc4<C>::type;
   extern __shared__ char tsm[];
   const int lp = pad16(l), TT = lp / 16, lq = lp + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  C* Qs = reinterpret_cast<C*>(tsm) + static_cast<int64_t>(wave) * 16 * lq;
-  const int64_t row0 = (static_cast<int64_t>(blockIdx.x) * nwave + wave) * 16;
-  for (int K = 0; K < TT; ++K) {
-    V acc;
-    const int col = K * 16 + li;
+  double* colacc = reinterpret_cast<double*>(tsm);         // lp column sums of this block
+  double* red = colacc + lp;                               // 4 x 16 wave partial sums
+  C* Rs = reinterpret_cast<C*>(red + 64);                  // lp x 16 strip of R
+  C* Ds = Rs + static_cast<int64_t>(lp) * 16;              // 16 x 16 inverse tile
+  C* Qs = Ds + 256 + static_cast<int64_t>(wave) * 16 * lq; // this wave's 16 rows of Q
+  for (int c = threadIdx.x; c < lp; c += blockDim.x) colacc[c] = 0.0;
+  const int64_t nblk = (rows + 16 * nwave - 1) / (16 * nwave);
+  for (int64_t bt = blockIdx.x; bt < nblk; bt += gridDim.x) {
+    const int64_t row0 = (bt * nwave + wave) * 16;
+    for (int K = 0; K < TT; ++K) {
+      const int col = K * 16 + li;
+      V acc;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = row0 + drow<C>(lk, r);
-      acc[r] = (row < rows && col < l) ? ld_as<C>(Y + row * ld + col) : C(0);
-    }
-    for (int J = 0; J < K; ++J) {
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + drow<C>(lk, r);
+        acc[r] = (row < rows && col < l) ? ld_as<C>(Y + row * ld + col) : C(0);
+      }
+      __syncthreads();  // previous strip no longer in use
+      for (int f = threadIdx.x; f < (K + 1) * 256; f += blockDim.x) {
+        const int r = f >> 4, c = f & 15;
+        Rs[f] = Rc[static_cast<int64_t>(r) * lp + K * 16 + c];
+      }
+      for (int f = threadIdx.x; f < 256; f += blockDim.x) Ds[f] = Dc[K * 256 + f];
+      __syncthreads();
+      for (int J = 0; J < K; ++J) {
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const C a = Qs[li * lq + J * 16 + kk * 4 + lk];
-        const C b = Rc[static_cast<int64_t>(J * 16 + kk * 4 + lk) * lp + K * 16 + li];
-        acc = mfma4(-a, b, acc);
+        for (int kk = 0; kk < 4; ++kk) {
+          const C a = Qs[li * lq + J * 16 + kk * 4 + lk];
+          const C b = Rs[(J * 16 + kk * 4 + lk) * 16 + li];
+          acc = mfma4(-a, b, acc);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Qs[drow<C>(lk, r) * lq + K * 16 + li] = acc[r];
+      wave_lds_sync();
+      V q = V{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) q = mfma4(Qs[li * lq + K * 16 + kk * 4 + lk], Ds[(kk * 4 + lk) * 16 + li], q);
+      wave_lds_sync();
+      double cs = 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        Qs[drow<C>(lk, r) * lq + K * 16 + li] = q[r];
+        const int64_t row = row0 + drow<C>(lk, r);
+        if (row < rows && col < l) {
+          T* dst = Y + row * ld + col;
+          Elem<T>::store(dst, q[r]);
+          if (colpart) cs += static_cast<double>(Elem<T>::load(dst));
+        }
+      }
+      wave_lds_sync();
+      if (colpart) {
+        cs += __shfl_xor(cs, 16, 64);
+        cs += __shfl_xor(cs, 32, 64);
+        if (lk == 0) red[wave * 16 + li] = cs;
+        __syncthreads();
+        if (threadIdx.x < 16) {
+          double t = 0.0;
+          for (int w = 0; w < nwave; ++w) t += red[w * 16 + threadIdx.x];
+          colacc[K * 16 + threadIdx.x] += t;
+        }
       }
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Qs[drow<C>(lk, r) * lq + K * 16 + li] = acc[r];
+  }
+  if (colpart) {
     __syncthreads();
-    V q = V{0, 0, 0, 0};
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const C a = Qs[li * lq + K * 16 + kk * 4 + lk];
-      const C b = Dc[K * 256 + (kk * 4 + lk) * 16 + li];
-      q = mfma4(a, b, q);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      Qs[drow<C>(lk, r) * lq + K * 16 + li] = q[r];
-      const int64_t row = row0 + drow<C>(lk, r);
-      if (row < rows && col < l) Elem<T>::store(Y + row * ld + col, q[r]);
-    }
-    __syncthreads();
+    for (int c = threadIdx.x; c < l; c += blockDim.x) colpart[static_cast<int64_t>(blockIdx.x) * l + c] = colacc[c];
   }
 }
 
@@ -472,18 +592,24 @@ __global__ void upper_mult_kernel(int lp, const double* A, const double* B, doub
 // ============================================================ one-sided Jacobi SVD
 
 constexpr int kJacobiMaxN = 1024;
-constexpr int kJacobiPerLane = kJacobiMaxN / 16;
+constexpr int kJacobiPerLane = 22;   // column elements per lane of a pair group
 
-// Each pair of columns is handled by a quarter wave (16 lanes).
+// One-sided (Hestenes) Jacobi on the columns of A, round-robin ("circle")
+// pair ordering: in each of the np-1 rounds every column is in exactly one
+// pair, pairs are independent.  A group of G lanes owns one pair: both
+// columns sit in its registers (kJacobiPerLane elements per lane), so a round
+// costs one round trip to memory; the rotation accumulator rows are touched
+// only when the pair is rotated.
+template <int G>
 __global__ __launch_bounds__(1024) void jacobi_kernel(int n, const double* A, int64_t lda, double* Uo,
                                                       double* s, double* Vo, double* work, int* sweeps_out) {
   const int np = n + (n & 1);
-  double* Wt = work;                                   // np x n
-  double* Jt = work + static_cast<int64_t>(np) * n;    // np x n
+  double* Wt = work;                                   // np x n : column p of A as row p
+  double* Jt = work + static_cast<int64_t>(np) * n;    // np x n : accumulated rotations
   double* sig = Jt + static_cast<int64_t>(np) * n;     // np
   int* rank = reinterpret_cast<int*>(sig + np);        // np
   const int tid = threadIdx.x;
-  const int q16 = tid >> 4, ql = tid & 15, nq = blockDim.x >> 4;
+  const int grp = tid / G, gl = tid % G, ngrp = blockDim.x / G;
   __shared__ int rotated;
   for (int64_t idx = tid; idx < static_cast<int64_t>(np) * n; idx += blockDim.x) {
     const int p = static_cast<int>(idx / n), i = static_cast<int>(idx % n);
@@ -491,29 +617,38 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int n, const double* A, in
     Jt[idx] = (p == i) ? 1.0 : 0.0;
   }
   __syncthreads();
-  const double tol = 2.0e-15;
+  // rotate while |cos| of the column pair exceeds n eps (below that the pair
+  // is orthogonal to working accuracy)
+  const double tol = static_cast<double>(n) * 2.220446049250313e-16;
   int sweep = 0;
   for (; sweep < 60; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int r = 0; r < np - 1; ++r) {
-      for (int k = q16; k < np / 2; k += nq) {
+      for (int k = grp; k < np / 2; k += ngrp) {
         const int a = (k == 0) ? 0 : ((k - 1 + r) % (np - 1)) + 1;
         const int b = ((np - 2 - k + r) % (np - 1)) + 1;
         double* wa = Wt + static_cast<int64_t>(a) * n;
         double* wb = Wt + static_cast<int64_t>(b) * n;
+        double x[kJacobiPerLane], y[kJacobiPerLane];
+#pragma unroll
+        for (int e = 0; e < kJacobiPerLane; ++e) {
+          const int i = gl + G * e;
+          x[e] = i < n ? wa[i] : 0.0;
+          y[e] = i < n ? wb[i] : 0.0;
+        }
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = ql; i < n; i += 16) {
-          const double x = wa[i], y = wb[i];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
+#pragma unroll
+        for (int e = 0; e < kJacobiPerLane; ++e) {
+          al += x[e] * x[e];
+          be += y[e] * y[e];
+          ga += x[e] * y[e];
         }
 #pragma unroll
-        for (int off = 8; off > 0; off >>= 1) {
-          al += __shfl_xor(al, off, 16);
-          be += __shfl_xor(be, off, 16);
-          ga += __shfl_xor(ga, off, 16);
+        for (int off = G / 2; off > 0; off >>= 1) {
+          al += __shfl_xor(al, off, G);
+          be += __shfl_xor(be, off, G);
+          ga += __shfl_xor(ga, off, G);
         }
         if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
@@ -522,15 +657,34 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int n, const double* A, in
           const double sn = c * t;
           double* ja = Jt + static_cast<int64_t>(a) * n;
           double* jb = Jt + static_cast<int64_t>(b) * n;
-          for (int i = ql; i < n; i += 16) {
-            const double x = wa[i], y = wb[i];
-            wa[i] = c * x - sn * y;
-            wb[i] = sn * x + c * y;
-            const double u = ja[i], v = jb[i];
-            ja[i] = c * u - sn * v;
-            jb[i] = sn * u + c * v;
+#pragma unroll
+          for (int e = 0; e < kJacobiPerLane; ++e) {
+            const int i = gl + G * e;
+            if (i < n) {
+              wa[i] = c * x[e] - sn * y[e];
+              wb[i] = sn * x[e] + c * y[e];
+            }
           }
-          if (ql == 0) rotated = 1;
+          // accumulator rows in chunks of 8 elements per lane (register budget)
+#pragma unroll
+          for (int e0 = 0; e0 < kJacobiPerLane; e0 += 8) {
+            double u[8], v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int i = gl + G * (e0 + e);
+              u[e] = (e0 + e < kJacobiPerLane && i < n) ? ja[i] : 0.0;
+              v[e] = (e0 + e < kJacobiPerLane && i < n) ? jb[i] : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int i = gl + G * (e0 + e);
+              if (e0 + e < kJacobiPerLane && i < n) {
+                ja[i] = c * u[e] - sn * v[e];
+                jb[i] = sn * u[e] + c * v[e];
+              }
+            }
+          }
+          if (gl == 0) rotated = 1;
         }
       }
       __syncthreads();
@@ -539,13 +693,13 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int n, const double* A, in
     __syncthreads();
     if (!any) break;
   }
-  for (int p = q16; p < np; p += nq) {
+  for (int p = grp; p < np; p += ngrp) {
     const double* wp = Wt + static_cast<int64_t>(p) * n;
     double acc = 0.0;
-    for (int i = ql; i < n; i += 16) acc += wp[i] * wp[i];
+    for (int i = gl; i < n; i += G) acc += wp[i] * wp[i];
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
-    if (ql == 0) sig[p] = sqrt(acc);
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+    if (gl == 0) sig[p] = sqrt(acc);
   }
   __syncthreads();
   for (int p = tid; p < n; p += blockDim.x) {
@@ -709,7 +863,9 @@ template void launch_gemm_tall<bf16>(int64_t, int, int, const bf16*, int64_t, in
 template <typename C>
 void launch_cholesky(int l, const double* G, int64_t ldg, double shift, double rel_tol, double* R64,
                      C* Rc, C* Dinv_c, int* flag, hipStream_t stream) {
-  hipLaunchKernelGGL((cholesky_kernel<C>), dim3(1), dim3(1024), 0, stream, l, G, ldg, shift, rel_tol,
+  const int T = pad16(l) / 16;
+  const size_t lds = T <= kCholLdsMaxTiles ? static_cast<size_t>(T) * (T + 1) / 2 * 256 * sizeof(double) : 0;
+  hipLaunchKernelGGL((cholesky_kernel<C>), dim3(1), dim3(1024), lds, stream, l, G, ldg, shift, rel_tol,
                      R64, Rc, Dinv_c, flag);
   ISVD_LAUNCH_CHECK();
 }
@@ -718,20 +874,31 @@ template void launch_cholesky<float>(int, const double*, int64_t, double, double
 
 template <typename T>
 void launch_trsm_tall(int64_t rows, int l, T* Y, int64_t ld, const typename ComputeOf<T>::type* Rc,
-                      const typename ComputeOf<T>::type* Dinv, hipStream_t stream) {
+                      const typename ComputeOf<T>::type* Dinv, double* colsum, double* work,
+                      hipStream_t stream) {
   using C = typename ComputeOf<T>::type;
   if (rows <= 0) return;
-  const int waves = sizeof(C) == 8 ? 2 : 4;
-  const size_t lds = static_cast<size_t>(waves) * 16 * (pad16(l) + 1) * sizeof(C);
+  auto lds_for = [&](int w) {
+    return (static_cast<size_t>(w) * 16 * (pad16(l) + 1) + static_cast<size_t>(pad16(l)) * 16 + 256) * sizeof(C) +
+           (static_cast<size_t>(pad16(l)) + 64) * sizeof(double);
+  };
+  int waves = sizeof(C) == 8 ? 2 : 4;
+  while (waves > 1 && lds_for(waves) > 160 * 1024) waves /= 2;
+  const size_t lds = lds_for(waves);
   ISVD_CHECK(lds <= 160 * 1024, ISVD_E_INVALID, "trsm: block too wide");
-  const int64_t blocks = ceil_div(rows, 16 * waves);
-  hipLaunchKernelGGL((trsm_tall_kernel<T, C>), dim3(static_cast<unsigned>(blocks)), dim3(64 * waves), lds,
-                     stream, rows, l, Y, ld, Rc, Dinv);
+  const int64_t nblk = ceil_div(rows, 16 * waves);
+  const int64_t grid = colsum ? (nblk < kTrsmParts ? nblk : kTrsmParts) : nblk;
+  hipLaunchKernelGGL((trsm_tall_kernel<T, C>), dim3(static_cast<unsigned>(grid)), dim3(64 * waves), lds, stream,
+                     rows, l, Y, ld, Rc, Dinv, colsum ? work : nullptr);
   ISVD_LAUNCH_CHECK();
+  if (colsum) {
+    hipLaunchKernelGGL(colpart_reduce_kernel, dim3(l), dim3(256), 0, stream, static_cast<int>(grid), l, work, colsum);
+    ISVD_LAUNCH_CHECK();
+  }
 }
-template void launch_trsm_tall<double>(int64_t, int, double*, int64_t, const double*, const double*, hipStream_t);
-template void launch_trsm_tall<float>(int64_t, int, float*, int64_t, const float*, const float*, hipStream_t);
-template void launch_trsm_tall<bf16>(int64_t, int, bf16*, int64_t, const float*, const float*, hipStream_t);
+template void launch_trsm_tall<double>(int64_t, int, double*, int64_t, const double*, const double*, double*, double*, hipStream_t);
+template void launch_trsm_tall<float>(int64_t, int, float*, int64_t, const float*, const float*, double*, double*, hipStream_t);
+template void launch_trsm_tall<bf16>(int64_t, int, bf16*, int64_t, const float*, const float*, double*, double*, hipStream_t);
 
 void launch_upper_mult(int l, const double* A, const double* B, double* Cm, int64_t ld, hipStream_t stream) {
   const int lp = pad16(l);
@@ -749,7 +916,14 @@ size_t jacobi_workspace_doubles(int n) {
 void launch_jacobi_svd(int n, const double* A, int64_t lda, double* U, double* s, double* V, double* work,
                        int* sweeps_out, hipStream_t stream) {
   ISVD_CHECK(n >= 1 && n <= kJacobiMaxN, ISVD_E_INVALID, "small svd: n out of range");
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
+  if (n <= 8 * kJacobiPerLane)
+    hipLaunchKernelGGL(jacobi_kernel<8>, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
+  else if (n <= 16 * kJacobiPerLane)
+    hipLaunchKernelGGL(jacobi_kernel<16>, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
+  else if (n <= 32 * kJacobiPerLane)
+    hipLaunchKernelGGL(jacobi_kernel<32>, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
+  else
+    hipLaunchKernelGGL(jacobi_kernel<64>, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
   ISVD_LAUNCH_CHECK();
 }
 

@@ -25,21 +25,23 @@ struct SvdState {
   // blocks (storage of the current phase)
   DevBuf qc, w, qr, y;
   // small FP64 matrices (padded lp x lp, ld lp)
-  DevBuf G, R1, R2, Rc, Rtmp, Rcc, Dc, flag, UR, ZR, sig, jac_work, rhs, left2, right2, gram_work, cn_work, sweeps;
-  int iterations = 0, applies = 0, bf16_iterations = 0, checks = 0, fallback = 0;
+  DevBuf G, R1, R2, Rc, Rtmp, Rcc, cs_work, sum_c, sum_r, Dc, flag, UR, ZR, sig, jac_work, rhs, left2, right2, gram_work, cn_work, sweeps;
+  int iterations = 0, applies = 0, bf16_iterations = 0, checks = 0, fallback = 0, ritz_steps = 0;
   double residual = -1.0;
   bool have_ritz = false;
   int ritz_iter = -1;
   void reset_counters() {
-    iterations = applies = bf16_iterations = checks = fallback = 0;
+    iterations = applies = bf16_iterations = checks = fallback = ritz_steps = 0;
     residual = -1.0;
     have_ritz = false;
     ritz_iter = -1;
   }
 };
 
+// CholeskyQR2 of Y in place; Rout (optional) receives R2 R1; colsum (optional,
+// l doubles) receives 1^T Q of the stored result.
 template <typename T>
-void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, hipStream_t stream) {
+void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* colsum, hipStream_t stream) {
   using C = typename ComputeOf<T>::type;
   const int l = st.l, lp = st.lp;
   st.G.ensure(static_cast<size_t>(l) * l * sizeof(double));
@@ -83,7 +85,10 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, hipStream_t 
       st.fallback = 1;
       if (passes == 2) passes = 3;
     }
-    launch_trsm_tall<T>(rows, l, Y, st.ld, st.Rcc.as<C>(), st.Dc.as<C>(), stream);
+    const bool last = pass + 1 == passes;
+    if (last && colsum) st.cs_work.ensure(trsm_colsum_workspace(l) * sizeof(double));
+    launch_trsm_tall<T>(rows, l, Y, st.ld, st.Rcc.as<C>(), st.Dc.as<C>(), last ? colsum : nullptr,
+                        last && colsum ? st.cs_work.as<double>() : nullptr, stream);
   }
   if (Rout) launch_upper_mult(l, st.R2.as<double>(), st.R1.as<double>(), Rout, lp, stream);
 }
@@ -98,6 +103,7 @@ void ritz(SvdState& st, hipStream_t stream) {
   launch_jacobi_svd(l, st.Rc.as<double>(), lp, st.UR.as<double>(), st.sig.as<double>(), st.ZR.as<double>(),
                     st.jac_work.as<double>(), st.sweeps.as<int>(), stream);
   st.have_ritz = true;
+  st.ritz_steps++;
 }
 
 // rho of the current Ritz triplets, given Y = M Qc of the next iteration.
@@ -177,14 +183,50 @@ void ensure_blocks(SvdState& st) {
 // Runs iterations in storage type T from the current Qc.  Returns 1 when the
 // Ritz triplets held in st satisfy the stopping rule of this phase (tolerance
 // `tol`, or the fixed count), 0 when max_iter was reached.
+// Iteration at which the next Rayleigh-Ritz step (and residual check) runs.
+// check_every > 0: a fixed stride.  check_every == 0: adaptive -- the residual
+// decays about geometrically, so the rate seen between the last two checks
+// predicts how many more iterations reach `tol`; the next check is placed at
+// 90% of that distance (at least 1 and at most 32 iterations ahead).
+struct CheckSchedule {
+  int every = 0;
+  int next = 0;
+  int last_t = -1;
+  double last_rho = -1.0;
+  int plan(int t, double rho, double tol) {
+    if (every > 0) return next = t + every;
+    int gap = 1;
+    if (last_t >= 0 && rho > 0.0 && last_rho > rho) {
+      const double rate = std::pow(rho / last_rho, 1.0 / (t - last_t));
+      const double need = std::log(tol / rho) / std::log(rate);
+      gap = static_cast<int>(0.9 * need);
+    } else if (last_t >= 0) {
+      gap = 2 * (t - last_t);
+    }
+    gap = gap < 1 ? 1 : (gap > 32 ? 32 : gap);
+    last_t = t;
+    last_rho = rho;
+    return next = t + gap;
+  }
+};
+
 template <typename T>
 int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, double tol, bool fixed, int t0,
               hipStream_t stream) {
   const int l = st.l;
-  const int every = prm->check_every > 0 ? prm->check_every : 1;
+  CheckSchedule sched;
+  sched.every = prm->check_every > 0 ? prm->check_every : 0;
+  sched.next = t0;
+  // 1^T Q of the blocks fed to the NE products come from the orthonormaliser
+  const bool ne = op->form == ISVD_FORM_NE;
+  if (ne) {
+    st.sum_c.ensure(static_cast<size_t>(l) * sizeof(double));
+    st.sum_r.ensure(static_cast<size_t>(l) * sizeof(double));
+  }
+  bool qc_sums = false;  // sum_c holds 1^T Qc (false for the start block)
   for (int t = t0;; ++t) {
     T* Y = st.y.as<T>();
-    apply_operator<T>(op, false, st.qc.as<T>(), st.ld, l, Y, st.ld, stream);
+    apply_operator<T>(op, false, st.qc.as<T>(), st.ld, l, Y, st.ld, stream, qc_sums ? st.sum_c.as<double>() : nullptr);
     st.applies++;
     if (!fixed && st.have_ritz && st.ritz_iter == t - 1) {
       st.residual = residual<T>(st, Y, stream);
@@ -192,6 +234,7 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
         st.iterations = t - 1;
         return 1;
       }
+      sched.plan(t - 1, st.residual, tol);
     }
     if (!fixed && t >= prm->max_iter) {
       // out of iterations: return the triplets of the last finished iteration
@@ -202,21 +245,22 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
       st.iterations = t - 1;
       return 0;
     }
-    orthonormalize<T>(st, Y, st.r, nullptr, stream);
+    orthonormalize<T>(st, Y, st.r, nullptr, ne ? st.sum_r.as<double>() : nullptr, stream);
     std::swap(st.qr.p, st.y.p);
     std::swap(st.qr.bytes, st.y.bytes);
-    apply_operator<T>(op, true, st.qr.as<T>(), st.ld, l, st.w.as<T>(), st.ld, stream);
+    apply_operator<T>(op, true, st.qr.as<T>(), st.ld, l, st.w.as<T>(), st.ld, stream, ne ? st.sum_r.as<double>() : nullptr);
     st.applies++;
-    orthonormalize<T>(st, st.w.as<T>(), st.c, st.Rc.as<double>(), stream);
+    orthonormalize<T>(st, st.w.as<T>(), st.c, st.Rc.as<double>(), ne ? st.sum_c.as<double>() : nullptr, stream);
     std::swap(st.qc.p, st.w.p);
     std::swap(st.qc.bytes, st.w.bytes);
+    qc_sums = ne;
     if (fixed && t >= prm->q) {
       ritz(st, stream);
       st.ritz_iter = t;
       st.iterations = t;
       return 1;
     }
-    if (!fixed && (t % every == 0)) {
+    if (!fixed && t >= sched.next) {
       ritz(st, stream);
       st.ritz_iter = t;
     }
@@ -320,6 +364,9 @@ isvd_status truncated_svd(isvd_operator* op, const isvd_svd_params* prm, void* U
     info->residual_checks = st.checks;
     info->used_fallback = st.fallback;
     info->residual = st.residual;
+    info->ritz_steps = st.ritz_steps;
+    info->jacobi_sweeps = 0;
+    if (st.sweeps.p) ISVD_HIP(hipMemcpy(&info->jacobi_sweeps, st.sweeps.p, sizeof(int), hipMemcpyDeviceToHost));
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   }
   if (rc == ISVD_E_NOT_CONVERGED) set_last_error("tolerance not reached within max_iter iterations");
@@ -334,7 +381,7 @@ void orthonormalize_block(int64_t rows, int cols, T* Y, int64_t ld, double* Rout
   st.lp = pad16(cols);
   st.ld = ld;
   st.Rc.ensure(static_cast<size_t>(st.lp) * st.lp * sizeof(double));
-  orthonormalize<T>(st, Y, rows, st.Rc.as<double>(), stream);
+  orthonormalize<T>(st, Y, rows, st.Rc.as<double>(), nullptr, stream);
   if (Rout) {
     launch_convert<double, double>(cols, cols, st.Rc.as<double>(), st.lp, Rout, cols, stream);
   }

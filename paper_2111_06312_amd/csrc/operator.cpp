@@ -58,7 +58,7 @@ double* column_sums(isvd_operator* op, const T* Y, int64_t rows, int64_t ldy, in
 
 template <typename T>
 void apply_ne(isvd_operator* op, bool transpose, const T* Y, int64_t ldy, int ncols, T* out, int64_t ldo,
-              hipStream_t stream) {
+              hipStream_t stream, const double* colsum_y) {
   const int K = op->K;
   const std::vector<double>& c = op->coeffs;  // c[j-1] = c_j
   const double lam = op->lambda;
@@ -66,7 +66,7 @@ void apply_ne(isvd_operator* op, bool transpose, const T* Y, int64_t ldy, int nc
   const auto* dinv = op->scale<T>();
   const int64_t n = op->n;
   const int64_t ld = block_ld(ncols);
-  double* s = column_sums<T>(op, Y, n, ldy, ncols, stream);
+  const double* s = colsum_y ? colsum_y : column_sums<T>(op, Y, n, ldy, ncols, stream);
 
   if (!transpose) {
     if (K == 1) {
@@ -222,13 +222,13 @@ void setup_csr(isvd_operator* op, Csr& csr, const int64_t* indptr, const int32_t
 
 template <typename T>
 void apply_operator(isvd_operator* op, bool transpose, const T* Y, int64_t ldy, int ncols, T* out,
-                    int64_t ldo, hipStream_t stream) {
-  if (op->form == ISVD_FORM_NE) apply_ne<T>(op, transpose, Y, ldy, ncols, out, ldo, stream);
+                    int64_t ldo, hipStream_t stream, const double* colsum_y) {
+  if (op->form == ISVD_FORM_NE) apply_ne<T>(op, transpose, Y, ldy, ncols, out, ldo, stream, colsum_y);
   else apply_featprop<T>(op, transpose, Y, ldy, ncols, out, ldo, stream);
 }
-template void apply_operator<double>(isvd_operator*, bool, const double*, int64_t, int, double*, int64_t, hipStream_t);
-template void apply_operator<float>(isvd_operator*, bool, const float*, int64_t, int, float*, int64_t, hipStream_t);
-template void apply_operator<bf16>(isvd_operator*, bool, const bf16*, int64_t, int, bf16*, int64_t, hipStream_t);
+template void apply_operator<double>(isvd_operator*, bool, const double*, int64_t, int, double*, int64_t, hipStream_t, const double*);
+template void apply_operator<float>(isvd_operator*, bool, const float*, int64_t, int, float*, int64_t, hipStream_t, const double*);
+template void apply_operator<bf16>(isvd_operator*, bool, const bf16*, int64_t, int, bf16*, int64_t, hipStream_t, const double*);
 
 void create_operator(const isvd_graph* g, const isvd_design* m, isvd_precision prec, hipStream_t stream,
                      isvd_operator* op) {

@@ -69,9 +69,10 @@ struct isvd_operator {
 namespace isvd {
 
 // out = M Y (transpose = false) or M^T Y, blocks of storage type T with ncols columns.
+// colsum_y (optional, NE form): 1^T Y in FP64 when the caller already has it.
 template <typename T>
 void apply_operator(isvd_operator* op, bool transpose, const T* Y, int64_t ldy, int ncols, T* out,
-                    int64_t ldo, hipStream_t stream);
+                    int64_t ldo, hipStream_t stream, const double* colsum_y = nullptr);
 
 void create_operator(const isvd_graph* g, const isvd_design* m, isvd_precision prec, hipStream_t stream,
                      isvd_operator* op);

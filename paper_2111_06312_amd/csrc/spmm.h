@@ -58,7 +58,7 @@ void launch_spmm_pass(const SpmmPass& p, hipStream_t stream);
 
 // Per-column FP64 sums s = 1^T Y of a rows x cols block (deterministic
 // two-stage reduction; partial has room for kColsumBlocks * cols doubles).
-constexpr int kColsumBlocks = 256;
+constexpr int kColsumBlocks = 1024;
 template <typename T>
 void launch_colsum(int64_t rows, int cols, const T* y, int64_t ld, double* partial, double* s,
                    hipStream_t stream);

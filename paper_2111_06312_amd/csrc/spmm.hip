@@ -333,27 +333,69 @@ template void launch_spmm_pass<bf16>(const SpmmPass&, hipStream_t);
 
 namespace {
 
+constexpr int kColsumMaxPerLane = 16;   // up to 1024 columns
+
+// Each wave streams whole rows (lane j owns columns j, j+64, ...) and keeps
+// FP64 sums in registers; waves of a block combine through LDS in order.
 template <typename T>
 __global__ __launch_bounds__(256) void colsum_partial_kernel(int64_t rows, int cols, const T* y,
                                                              int64_t ld, double* partial) {
-  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = per * blockIdx.x;
-  const int64_t r1 = r0 + per < rows ? r0 + per : rows;
-  for (int c0 = 0; c0 < cols; c0 += blockDim.x) {
-    const int c = c0 + threadIdx.x;
-    if (c >= cols) continue;
-    double s = 0.0;
-    for (int64_t r = r0; r < r1; ++r) s += static_cast<double>(Elem<T>::load(y + r * ld + c));
-    partial[static_cast<int64_t>(blockIdx.x) * cols + c] = s;
+  __shared__ double red[4][1024];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int per_lane = (cols + 63) / 64;
+  double acc[kColsumMaxPerLane];
+#pragma unroll
+  for (int m = 0; m < kColsumMaxPerLane; ++m) acc[m] = 0.0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 4;
+  int64_t r = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+  // four rows in flight per wave
+  for (; r + 3 * stride < rows; r += 4 * stride) {
+    double x[4][kColsumMaxPerLane];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T* row = y + (r + u * stride) * ld;
+#pragma unroll
+      for (int m = 0; m < kColsumMaxPerLane; ++m) {
+        const int c = lane + 64 * m;
+        x[u][m] = (m < per_lane && c < cols) ? static_cast<double>(Elem<T>::load(row + c)) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int m = 0; m < kColsumMaxPerLane; ++m) acc[m] += x[u][m];
   }
+  for (; r < rows; r += stride) {
+    const T* row = y + r * ld;
+#pragma unroll
+    for (int m = 0; m < kColsumMaxPerLane; ++m) {
+      const int c = lane + 64 * m;
+      if (m < per_lane && c < cols) acc[m] += static_cast<double>(Elem<T>::load(row + c));
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kColsumMaxPerLane; ++m) {
+    const int c = lane + 64 * m;
+    if (m < per_lane && c < cols) red[wave][c] = acc[m];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < cols; c += blockDim.x)
+    partial[static_cast<int64_t>(blockIdx.x) * cols + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
 }
 
-__global__ void colsum_final_kernel(int nparts, int cols, const double* partial, double* s) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// s[c] = sum over parts: one block per column, strided partial sums, fixed-order tree.
+__global__ __launch_bounds__(256) void colsum_final_kernel(int nparts, int cols, const double* partial, double* s) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
   double acc = 0.0;
-  for (int b = 0; b < nparts; ++b) acc += partial[static_cast<int64_t>(b) * cols + c];
-  s[c] = acc;
+  for (int q = threadIdx.x; q < nparts; q += 256) acc += partial[static_cast<int64_t>(q) * cols + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s[c] = red[0];
 }
 
 }  // namespace
@@ -361,12 +403,12 @@ __global__ void colsum_final_kernel(int nparts, int cols, const double* partial,
 template <typename T>
 void launch_colsum(int64_t rows, int cols, const T* y, int64_t ld, double* partial, double* s,
                    hipStream_t stream) {
-  int nparts = static_cast<int>(rows < kColsumBlocks ? (rows > 0 ? rows : 1) : kColsumBlocks);
-  hipLaunchKernelGGL(colsum_partial_kernel<T>, dim3(nparts), dim3(256), 0, stream, rows, cols, y, ld,
-                     partial);
+  ISVD_CHECK(cols >= 1 && cols <= 1024, ISVD_E_INVALID, "colsum: cols out of range");
+  const int64_t want = ceil_div(rows > 0 ? rows : 1, 16);
+  const int nparts = static_cast<int>(want < kColsumBlocks ? want : kColsumBlocks);
+  hipLaunchKernelGGL(colsum_partial_kernel<T>, dim3(nparts), dim3(256), 0, stream, rows, cols, y, ld, partial);
   ISVD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(colsum_final_kernel, dim3(static_cast<unsigned>(ceil_div(cols, 256))), dim3(256),
-                     0, stream, nparts, cols, partial, s);
+  hipLaunchKernelGGL(colsum_final_kernel, dim3(cols), dim3(256), 0, stream, nparts, cols, partial, s);
   ISVD_LAUNCH_CHECK();
 }
 

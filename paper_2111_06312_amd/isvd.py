@@ -52,7 +52,7 @@ class _SvdParams(ct.Structure):
 class _SvdInfo(ct.Structure):
     _fields_ = [("iterations", ct.c_int), ("applies", ct.c_int), ("bf16_iterations", ct.c_int),
                 ("residual_checks", ct.c_int), ("used_fallback", ct.c_int), ("residual", ct.c_double),
-                ("seconds", ct.c_double)]
+                ("seconds", ct.c_double), ("ritz_steps", ct.c_int), ("jacobi_sweeps", ct.c_int)]
 
 
 @dataclass
@@ -65,6 +65,8 @@ class SvdInfo:
     residual: float
     seconds: float
     status: int = 0
+    ritz_steps: int = 0
+    jacobi_sweeps: int = 0
 
 
 def load():
@@ -186,7 +188,7 @@ class Operator:
                                       _ptr(out), _ld(out), _stream()))
         return out
 
-    def truncated_svd(self, k, p, q=2, tol=0.0, max_iter=1000, check_every=1, seed=0, omega=None,
+    def truncated_svd(self, k, p, q=2, tol=0.0, max_iter=1000, check_every=0, seed=0, omega=None,
                       fp32_switch_tol=0.0, allow_not_converged=False):
         """(U, S, V, info) through isvd_truncated_svd."""
         r, c = self.shape
@@ -205,7 +207,8 @@ class Operator:
                                             ct.byref(info), _stream()),
                     allow=(ISVD_E_NOT_CONVERGED,) if allow_not_converged else ())
         return U, S, V, SvdInfo(info.iterations, info.applies, info.bf16_iterations, info.residual_checks,
-                                info.used_fallback, info.residual, info.seconds, st)
+                                info.used_fallback, info.residual, info.seconds, st, info.ritz_steps,
+                                info.jacobi_sweeps)
 
 
 def profile_spmm(on=True):

@@ -146,7 +146,13 @@ def main():
         try:
             with open(args.traffic_json) as fh:
                 tj = json.load(fh)
-            if tj.get("workload") == cfg.name and tj.get("precision") == prec_name:
+            import hashlib
+            src = os.path.join(ROOT, "paper_2111_06312_amd", "csrc", "spmm.hip")
+            with open(src, "rb") as fh:
+                cur = hashlib.sha256(fh.read()).hexdigest()[:16]
+            # counters describe the kernel they were taken on: stale once its source changed
+            if (tj.get("workload") == cfg.name and tj.get("precision") == prec_name
+                    and tj.get("spmm_source_sha256_16") == cur):
                 traffic = tj.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None

@@ -144,8 +144,9 @@ isvd_status isvd_matmul_block(isvd_operator* op, int transpose, const void* Y, i
  *  omega     : optional device c x l start block (operator precision, leading
  *              dimension ld_omega), used verbatim.
  *  fp32_switch_tol : BF16 operators only; when > 0 the iteration continues
- *              in FP32 once rho <= fp32_switch_tol (BF16 alone cannot reach
- *              small residuals).  U and V are then float. */
+ *              in FP32 once rho <= fp32_switch_tol, or once a check improves rho
+ *              by less than 10% (the BF16 rounding floor; BF16 alone cannot reach
+ *              small residuals).  U and V are float for BF16 operators. */
 typedef struct {
   int k;
   int p;
@@ -157,6 +158,7 @@ typedef struct {
   const void* omega;
   int64_t ld_omega;
   double fp32_switch_tol;
+  int bf16_max_iter;     /* BF16 operators: > 0 also ends the BF16 phase after this many iterations */
 } isvd_svd_params;
 
 typedef struct {

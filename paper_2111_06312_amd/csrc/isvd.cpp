@@ -210,9 +210,12 @@ struct CheckSchedule {
   }
 };
 
+// stall_ratio > 0: also stop (returning 2) when a check improves rho by less
+// than that factor over the previous check -- the precision floor of the
+// block storage has been reached.
 template <typename T>
 int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, double tol, bool fixed, int t0,
-              hipStream_t stream) {
+              hipStream_t stream, double stall_ratio = 0.0, int phase_cap = 0) {
   const int l = st.l;
   CheckSchedule sched;
   sched.every = prm->check_every > 0 ? prm->check_every : 0;
@@ -234,7 +237,15 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
         st.iterations = t - 1;
         return 1;
       }
+      if (stall_ratio > 0.0 && sched.last_rho > 0.0 && st.residual > stall_ratio * sched.last_rho) {
+        st.iterations = t - 1;
+        return 2;
+      }
       sched.plan(t - 1, st.residual, tol);
+    }
+    if (!fixed && phase_cap > 0 && t >= phase_cap && st.have_ritz && st.ritz_iter == t - 1) {
+      st.iterations = t - 1;
+      return 2;
     }
     if (!fixed && t >= prm->max_iter) {
       // out of iterations: return the triplets of the last finished iteration
@@ -260,7 +271,7 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
       st.iterations = t;
       return 1;
     }
-    if (!fixed && t >= sched.next) {
+    if (!fixed && (t >= sched.next || (phase_cap > 0 && t + 1 >= phase_cap))) {
       ritz(st, stream);
       st.ritz_iter = t;
     }
@@ -299,7 +310,8 @@ isvd_status svd_bf16(isvd_operator* op, const isvd_svd_params* prm, void* U, int
     return ok ? ISVD_OK : ISVD_E_NOT_CONVERGED;
   }
   // BF16 until rho <= fp32_switch_tol, then widen Qc and continue in FP32.
-  const int ok16 = run_phase<bf16>(st, op, prm, prm->fp32_switch_tol, false, 0, stream);
+  const int ok16 = run_phase<bf16>(st, op, prm, prm->fp32_switch_tol, false, 0, stream,
+                                  prm->bf16_max_iter > 0 ? 0.0 : 0.9, prm->bf16_max_iter);
   if (!ok16) {
     st.bf16_iterations = st.iterations + 1;
     finalize<bf16, float>(st, op, U, ldu, S, V, ldv, stream);

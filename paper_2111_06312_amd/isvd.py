@@ -46,7 +46,7 @@ class _Design(ct.Structure):
 class _SvdParams(ct.Structure):
     _fields_ = [("k", ct.c_int), ("p", ct.c_int), ("q", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
                 ("check_every", ct.c_int), ("seed", ct.c_uint64), ("omega", ct.c_void_p),
-                ("ld_omega", ct.c_int64), ("fp32_switch_tol", ct.c_double)]
+                ("ld_omega", ct.c_int64), ("fp32_switch_tol", ct.c_double), ("bf16_max_iter", ct.c_int)]
 
 
 class _SvdInfo(ct.Structure):
@@ -189,7 +189,7 @@ class Operator:
         return out
 
     def truncated_svd(self, k, p, q=2, tol=0.0, max_iter=1000, check_every=0, seed=0, omega=None,
-                      fp32_switch_tol=0.0, allow_not_converged=False):
+                      fp32_switch_tol=0.0, bf16_max_iter=0, allow_not_converged=False):
         """(U, S, V, info) through isvd_truncated_svd."""
         r, c = self.shape
         out_dtype = torch.float32 if self.precision == BF16 else self.dtype
@@ -199,7 +199,8 @@ class Operator:
         S = torch.empty(k, dtype=torch.float64, device=dev)
         prm = _SvdParams(k=k, p=p, q=q, tol=tol, max_iter=max_iter, check_every=check_every, seed=seed,
                          omega=_ptr(omega) if omega is not None else None,
-                         ld_omega=_ld(omega) if omega is not None else 0, fp32_switch_tol=fp32_switch_tol)
+                         ld_omega=_ld(omega) if omega is not None else 0, fp32_switch_tol=fp32_switch_tol,
+                         bf16_max_iter=bf16_max_iter)
         if omega is not None:
             assert omega.dtype == self.dtype and omega.shape == (c, k + p)
         info = _SvdInfo()
@@ -269,3 +270,69 @@ def exported_symbols_from_header(path=None):
     text = open(path).read()
     text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
     return sorted(set(re.findall(r"\b(isvd_[a-z0-9_]+)\s*\(", text)))
+
+
+def features(op):
+    """n x 16 FP32 structural features of an NE operator's nodes (isvd_ws_features)."""
+    load()
+    F = torch.empty((op.shape[1], 16), dtype=torch.float32, device=op._indptr.device)
+    _check(_lib.isvd_ws_features(op.handle, _ptr(F), _stream()))
+    return F
+
+
+class WarmStart:
+    """The warm-start network (isvd_ws_*): 16 -> 128 -> 128 -> k MLP."""
+
+    def __init__(self, k, seed=0):
+        load()
+        h = ct.c_void_p()
+        _check(_lib.isvd_ws_create(k, seed, ct.byref(h)))
+        self.handle = h
+        self.k = k
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.isvd_ws_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self):
+        return _lib.isvd_ws_num_params(self.handle)
+
+    def get_params(self):
+        out = np.empty(self.num_params, dtype=np.float32)
+        _check(_lib.isvd_ws_get_params(self.handle, out.ctypes.data_as(ct.c_void_p)))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        assert theta.size == self.num_params
+        _check(_lib.isvd_ws_set_params(self.handle, theta.ctypes.data_as(ct.c_void_p)))
+
+    def forward(self, F):
+        Z = torch.empty((F.shape[0], self.k), dtype=torch.float32, device=F.device)
+        _check(_lib.isvd_ws_forward(self.handle, F.shape[0], _ptr(F), _ptr(Z), self.k, _stream()))
+        return Z
+
+    def train_step(self, F, V, lr=0.0, want_grad=False):
+        """(loss, grad or None); applies an Adam step when lr > 0."""
+        loss = ct.c_double()
+        grad = np.empty(self.num_params, dtype=np.float32) if want_grad else None
+        _check(_lib.isvd_ws_train_step(self.handle, F.shape[0], _ptr(F), _ptr(V), _ld(V), float(lr), ct.byref(loss),
+                                       grad.ctypes.data_as(ct.c_void_p) if want_grad else None, _stream()))
+        return loss.value, grad
+
+    def omega(self, op, F, p, seed=0):
+        """(start block [MLP(F) | Gaussian p columns] in op's precision, used_fallback)."""
+        c = op.shape[1]
+        om = torch.empty((c, self.k + p), dtype=op.dtype, device=F.device)
+        fb = ct.c_int()
+        _check(_lib.isvd_ws_omega(self.handle, op.handle, _ptr(F), p, seed, _ptr(om), _ld(om), ct.byref(fb),
+                                  _stream()))
+        return om, bool(fb.value)

@@ -1,0 +1,116 @@
+"""Warm-start kernels against the FP64 oracle: structural features, forward,
+subspace loss, gradients of every parameter, Adam, and the Gaussian fallback."""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import to_dev, to_np
+from oracle import mlp
+from oracle.graph import adjacency
+from synth import chung_lu_graph
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(*a):
+    print("CASE", *a, flush=True)
+
+
+def _flat(params):
+    return np.concatenate([p.reshape(-1) for p in params]).astype(np.float32)
+
+
+def _unflat(theta, k):
+    sizes = [(16, 128), (128,), (128, 128), (128,), (128, k), (k,)]
+    out, o = [], 0
+    for s in sizes:
+        n = int(np.prod(s))
+        out.append(theta[o:o + n].astype(np.float64).reshape(s))
+        o += n
+    return out
+
+
+@pytest.fixture(scope="module")
+def small_graph():
+    return chung_lu_graph(3000, 2.5, 8.0, seed=41)
+
+
+def test_features_match_oracle(gpu_lib, small_graph):
+    _case("features")
+    g = small_graph
+    op = gpu_lib.Operator(g, form="ne", coeffs=[1.0], lam=0.0, precision=gpu_lib.FP32)
+    F = to_np(gpu_lib.features(op))
+    want = mlp.structural_features(adjacency(g.n, g.indptr, g.indices))
+    assert np.abs(F - want).max() < 2e-5
+    op.close()
+
+
+def test_forward_loss_and_gradients_match_oracle(gpu_lib, small_graph):
+    _case("mlp grads")
+    g = small_graph
+    k, n = 8, g.n
+    rng = np.random.default_rng(3)
+    params = mlp.init_params(k, seed=7)
+    for p in params[1::2]:
+        p += 0.1 * rng.standard_normal(p.shape)
+    theta = _flat(params)
+    params32 = _unflat(theta, k)      # the exact FP32 values the GPU holds
+    f = mlp.structural_features(adjacency(g.n, g.indptr, g.indices)).astype(np.float32).astype(np.float64)
+    v, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    v = v.astype(np.float32).astype(np.float64)
+    ws = gpu_lib.WarmStart(k, seed=1)
+    ws.set_params(theta)
+    assert np.array_equal(ws.get_params(), theta)
+    Fd, Vd = to_dev(f, torch.float32), to_dev(v, torch.float32)
+    z = to_np(ws.forward(Fd)).astype(np.float64)
+    zo, cache = mlp.forward(params32, f)
+    assert np.abs(z - zo).max() <= 1e-4 * np.abs(zo).max()
+    loss, grad = ws.train_step(Fd, Vd, lr=0.0, want_grad=True)
+    lo, dz = mlp.subspace_loss(zo, v)
+    go = mlp.backward(params32, cache, dz)
+    assert abs(loss - lo) <= 1e-4
+    for gg, want in zip(_unflat(grad, k), go):
+        assert np.abs(gg - want).max() <= 1e-3 * np.abs(want).max() + 1e-7
+    ws.close()
+
+
+def test_adam_step_matches_oracle(gpu_lib, small_graph):
+    _case("adam")
+    g = small_graph
+    k = 4
+    ws = gpu_lib.WarmStart(k, seed=2)
+    theta = ws.get_params()
+    f = mlp.structural_features(adjacency(g.n, g.indptr, g.indices)).astype(np.float32)
+    v, _ = np.linalg.qr(np.random.default_rng(5).standard_normal((g.n, k)))
+    Fd, Vd = to_dev(f, torch.float32), to_dev(v.astype(np.float32), torch.float32)
+    _, grad = ws.train_step(Fd, Vd, lr=0.0, want_grad=True)
+    ws.train_step(Fd, Vd, lr=1e-2)
+    after = ws.get_params()
+    p = [theta.astype(np.float64)]
+    mlp.adam_step(p, [grad.astype(np.float64)], [np.zeros_like(p[0])], [np.zeros_like(p[0])], t=1, lr=1e-2)
+    assert np.abs(after - p[0]).max() <= 1e-5
+    ws.close()
+
+
+def test_omega_uses_network_and_falls_back(gpu_lib, small_graph):
+    _case("omega")
+    g = small_graph
+    k, p = 6, 4
+    op = gpu_lib.Operator(g, form="ne", coeffs=[0.5, 0.5], lam=0.1, precision=gpu_lib.FP32)
+    F = gpu_lib.features(op)
+    ws = gpu_lib.WarmStart(k, seed=3)
+    om, fb = ws.omega(op, F, p, seed=9)
+    assert not fb
+    z = to_np(ws.forward(F))
+    assert np.array_equal(to_np(om)[:, :k], z)
+    gauss = to_np(gpu_lib.gaussian_block(g.n, k + p, 9, torch.float32))
+    assert np.array_equal(to_np(om)[:, k:], gauss[:, k:])
+    bad = ws.get_params()
+    bad[:] = np.nan
+    ws.set_params(bad)
+    om, fb = ws.omega(op, F, p, seed=9)
+    assert fb
+    assert np.array_equal(to_np(om), gauss)
+    ws.close()
+    op.close()

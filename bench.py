@@ -47,6 +47,10 @@ def parse():
                     help="first copy a 1 GiB device buffer 3 times (a plain copy kernel of known size, "
                          "to scale hardware byte counters)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "spmm_traffic.json"))
+    ap.add_argument("--warmstart", default=None,
+                    help="trained warm-start parameters (.npy); each step then computes the features, the "
+                         "network's start block and the iSVD from it, and the same steps with a Gaussian "
+                         "start block are timed for comparison")
     return ap.parse_args()
 
 
@@ -115,6 +119,34 @@ def main():
                       precision=precision)
     kw = dict(tol=args.tol, max_iter=args.max_iter, check_every=args.check_every,
               fp32_switch_tol=args.fp32_switch_tol if precision == lib.BF16 else 0.0)
+    ws = None
+    if args.warmstart:
+        import numpy as np
+        ws = lib.WarmStart(cfg.k, seed=0)
+        ws.set_params(np.load(args.warmstart))
+
+    def one_step(seed, warm):
+        if warm:
+            F = lib.features(op)
+            om, fb = ws.omega(op, F, cfg.p, seed=seed)
+            out = op.truncated_svd(cfg.k, cfg.p, omega=om, allow_not_converged=True, **kw)
+            return out[3], fb
+        return op.truncated_svd(cfg.k, cfg.p, seed=seed, allow_not_converged=True, **kw)[3], False
+
+    gauss = None
+    if ws is not None:
+        # the Gaussian-start comparison: same seeds, same tolerance
+        g_times, g_its = [], []
+        for s_ in range(args.steps):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            info, _ = one_step(s_, False)
+            torch.cuda.synchronize()
+            g_times.append(time.perf_counter() - ts)
+            g_its.append(info.iterations)
+            print(f"[bench] gaussian start {s_}: {g_times[-1]:.3f} s, iterations {info.iterations}, "
+                  f"rho {info.residual:.2e}", file=sys.stderr, flush=True)
+        gauss = {"mean_s": round(sum(g_times) / len(g_times), 4), "iterations": g_its}
     infos = []
     for w in range(args.warmup):
         _, S, _, info = op.truncated_svd(cfg.k, cfg.p, seed=1000 + w, allow_not_converged=True, **kw)
@@ -124,9 +156,11 @@ def main():
     lib.profile_spmm(True)
     times = []
     t_start = time.perf_counter()
+    fallbacks = 0
     for s in range(args.steps):
         ts = time.perf_counter()
-        _, S, _, info = op.truncated_svd(cfg.k, cfg.p, seed=s, allow_not_converged=True, **kw)
+        info, fb = one_step(s, ws is not None)
+        fallbacks += int(fb)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - ts)
         infos.append(info)
@@ -174,7 +208,10 @@ def main():
                    "K": cfg.K, "lambda": cfg.lam, "tol": args.tol,
                    "iterations": [i.iterations for i in infos], "applies": [i.applies for i in infos],
                    "residual": [i.residual for i in infos], "converged": converged,
-                   "median_step_s": round(statistics.median(times), 4)},
+                   "median_step_s": round(statistics.median(times), 4),
+                   "start_block": "learned warm start" if ws is not None else "gaussian",
+                   **({"gaussian_start": gauss, "warmstart_fallbacks": fallbacks,
+                       "warmstart_weights": os.path.relpath(args.warmstart, ROOT)} if ws is not None else {})},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "kernel": "spmm_pass_kernel", "avg_launch_us": round(avg_launch_s * 1e6, 2),
@@ -182,7 +219,7 @@ def main():
                      "compulsory_gbps": round(compulsory, 1),
                      "spmm_share_of_step": round(spmm_ms / 1e3 / total, 4)},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and cfg.n <= 500_000:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         last = infos[-1]
         orths = 2 * 2 * (last.iterations + 1)

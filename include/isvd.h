@@ -159,6 +159,9 @@ typedef struct {
   int64_t ld_omega;
   double fp32_switch_tol;
   int bf16_max_iter;     /* BF16 operators: > 0 also ends the BF16 phase after this many iterations */
+  int orth_passes;       /* 2: CholeskyQR2 in every iteration; otherwise one Cholesky pass (Algorithm 2)
+                            in iterations whose bases only feed the next product, CholeskyQR2 before
+                            every Rayleigh-Ritz step */
 } isvd_svd_params;
 
 typedef struct {
@@ -264,10 +267,13 @@ isvd_status isvd_ws_forward(isvd_warmstart* ws, int64_t n, const float* F, float
                             void* stream);
 
 /* Loss and parameter gradient for one graph: forward, subspace loss
- * L = tr((Z^T Z)^-1 Z^T (I - V V^T) Z) / k against orthonormal V (n x k,
- * ld ldv, FP32 device), backward.  grad_out: optional host array of
- * isvd_ws_num_params floats.  loss_out: host.  If lr > 0 an Adam step
- * (beta1 0.9, beta2 0.999, eps 1e-8) is applied.  Synchronises. */
+ * L = tr(G^-1 Z^T (I - V V^T) Z) / k, G = Z^T Z + mu I, mu = 1e-3 tr(Z^T Z)/k
+ * (a ridge held constant in the gradient; mu = 0 would give the mean sin^2 of
+ * the principal angles) against orthonormal V (n x k, ld ldv, FP32 device),
+ * backward.  grad_out: optional host array of isvd_ws_num_params floats.
+ * loss_out: host.  If lr > 0 an Adam step (beta1 0.9, beta2 0.999, eps 1e-8)
+ * is applied.  ISVD_E_NOT_SPD (and no update) if G is not positive definite.
+ * Synchronises. */
 isvd_status isvd_ws_train_step(isvd_warmstart* ws, int64_t n, const float* F, const float* V,
                                int64_t ldv, double lr, double* loss_out, float* grad_out,
                                void* stream);

@@ -33,7 +33,7 @@ __device__ inline C ld_as(const T* p) { return static_cast<C>(Elem<T>::load(p));
 
 constexpr int kGramWaves = 8;
 constexpr int kGramThreads = 64 * kGramWaves;
-constexpr int kGramMaxTPW = 24;      // tiles per wave of the largest instantiation
+constexpr int kGramMaxTPW = 12;      // tiles per wave of the largest instantiation
 constexpr int kGramPrefetch = 16;    // staged elements per thread per row chunk
 constexpr int kGramMaxParts = 256;
 
@@ -74,10 +74,11 @@ __global__ __launch_bounds__(kGramThreads) void gram_partial_kernel(int64_t rows
   v4d acc[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
+    // surplus slots recompute the group's last tile (no branch around the
+    // MFMAs) and are not stored
     const int idx = gfirst + wave + kGramWaves * t;
     act[t] = idx < glast;
-    ti[t] = tj[t] = 0;
-    if (act[t]) decode_tile(idx, same, tm, tp, ti[t], tj[t]);
+    decode_tile(act[t] ? idx : glast - 1, same, tm, tp, ti[t], tj[t]);
     acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
   }
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per_block;
@@ -114,9 +115,7 @@ __global__ __launch_bounds__(kGramThreads) void gram_partial_kernel(int64_t rows
     for (int kk = 0; kk < rb / 4; ++kk) {
       const int kr = kk * 4 + lk;
 #pragma unroll
-      for (int t = 0; t < TPW; ++t) {
-        if (act[t]) acc[t] = mfma4(As[kr * mp + ti[t] * 16 + li], Bs[kr * pp + tj[t] * 16 + li], acc[t]);
-      }
+      for (int t = 0; t < TPW; ++t) acc[t] = mfma4(As[kr * mp + ti[t] * 16 + li], Bs[kr * pp + tj[t] * 16 + li], acc[t]);
     }
   }
   double* part = partial + static_cast<int64_t>(blockIdx.x) * mp * pp;
@@ -197,7 +196,6 @@ void gram_impl(int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B
   const GramPlan g = plan_gram(rows, m, p, same);
   if (g.tpw <= 4) gram_launch<TA, TB, 4>(g, rows, m, p, A, lda, B, ldb, same, work, stream);
   else if (g.tpw <= 8) gram_launch<TA, TB, 8>(g, rows, m, p, A, lda, B, ldb, same, work, stream);
-  else if (g.tpw <= 12) gram_launch<TA, TB, 12>(g, rows, m, p, A, lda, B, ldb, same, work, stream);
   else gram_launch<TA, TB, kGramMaxTPW>(g, rows, m, p, A, lda, B, ldb, same, work, stream);
   const int64_t total = static_cast<int64_t>(m) * p;
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(total, 64))), dim3(256),
@@ -723,6 +721,138 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int n, const double* A, in
   if (tid == 0 && sweeps_out) *sweeps_out = sweep;
 }
 
+// ---------------------------------------------------------------- block Jacobi
+//
+// Columns are grouped in blocks of B; each launch is one round of the
+// round-robin over blocks, one workgroup per block pair.  A workgroup loads
+// its 2B columns of W (and the matching rows of the rotation accumulator J)
+// into LDS and runs one full one-sided Jacobi sweep among them (2B-1 inner
+// rounds of B independent pairs, one wave per pair).  flags[0] = converged
+// (every later launch returns at once), flags[1 + s] = rotated in sweep s.
+
+constexpr int kBJThreads = 1024;
+
+template <int B>
+__global__ __launch_bounds__(kBJThreads) void bjacobi_round_kernel(int n, int nb, int round, int sweep, double* Wt,
+                                                                   double* Jt, int* flags) {
+  if (flags[0]) return;
+  extern __shared__ double bjs[];
+  double* Ws = bjs;                                  // 2B x n
+  double* Js = bjs + static_cast<int64_t>(2 * B) * n;  // 2B x n
+  __shared__ int any_rot;
+  const int w = blockIdx.x;
+  const int pa = (w == 0) ? 0 : ((w - 1 + round) % (nb - 1)) + 1;
+  const int pb = ((nb - 2 - w + round) % (nb - 1)) + 1;
+  const int blk[2] = {pa, pb};
+  for (int64_t f = threadIdx.x; f < static_cast<int64_t>(2 * B) * n; f += blockDim.x) {
+    const int lc = static_cast<int>(f / n), i = static_cast<int>(f % n);
+    const int64_t gc = static_cast<int64_t>(blk[lc / B]) * B + (lc % B);
+    Ws[f] = Wt[gc * n + i];
+    Js[f] = Jt[gc * n + i];
+  }
+  if (threadIdx.x == 0) any_rot = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double tol = static_cast<double>(n) * 2.220446049250313e-16;
+  constexpr int P = 2 * B;  // local players
+  for (int r = 0; r < P - 1; ++r) {
+    for (int k = wave; k < B; k += kBJThreads / 64) {
+      const int a = (k == 0) ? 0 : ((k - 1 + r) % (P - 1)) + 1;
+      const int b = ((P - 2 - k + r) % (P - 1)) + 1;
+      double* wa = Ws + static_cast<int64_t>(a) * n;
+      double* wb = Ws + static_cast<int64_t>(b) * n;
+      double al = 0.0, be = 0.0, ga = 0.0;
+      for (int i = lane; i < n; i += 64) {
+        const double x = wa[i], y = wb[i];
+        al += x * x;
+        be += y * y;
+        ga += x * y;
+      }
+      al = wave_sum(al);
+      be = wave_sum(be);
+      ga = wave_sum(ga);
+      if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double sn = c * t;
+        double* ja = Js + static_cast<int64_t>(a) * n;
+        double* jb = Js + static_cast<int64_t>(b) * n;
+        for (int i = lane; i < n; i += 64) {
+          const double x = wa[i], y = wb[i];
+          wa[i] = c * x - sn * y;
+          wb[i] = sn * x + c * y;
+          const double u = ja[i], v = jb[i];
+          ja[i] = c * u - sn * v;
+          jb[i] = sn * u + c * v;
+        }
+        if (lane == 0) any_rot = 1;
+      }
+    }
+    __syncthreads();
+  }
+  for (int64_t f = threadIdx.x; f < static_cast<int64_t>(2 * B) * n; f += blockDim.x) {
+    const int lc = static_cast<int>(f / n), i = static_cast<int>(f % n);
+    const int64_t gc = static_cast<int64_t>(blk[lc / B]) * B + (lc % B);
+    Wt[gc * n + i] = Ws[f];
+    Jt[gc * n + i] = Js[f];
+  }
+  if (threadIdx.x == 0 && any_rot) flags[1 + sweep] = 1;
+}
+
+__global__ void bjacobi_init_kernel(int n, int np, const double* A, int64_t lda, double* Wt, double* Jt, int* flags,
+                                    int nflags) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx < nflags) flags[idx] = 0;
+  if (idx >= static_cast<int64_t>(np) * n) return;
+  const int p = static_cast<int>(idx / n), i = static_cast<int>(idx % n);
+  Wt[idx] = p < n ? A[static_cast<int64_t>(i) * lda + p] : 0.0;
+  Jt[idx] = (p == i) ? 1.0 : 0.0;
+}
+
+__global__ void bjacobi_check_kernel(int sweep, int* flags) {
+  if (threadIdx.x == 0 && !flags[0] && !flags[1 + sweep]) {
+    flags[0] = 1;
+    flags[1 + 64] = sweep;  // sweeps taken (the last one rotated nothing)
+  }
+}
+
+// Singular values (column norms), descending order, U = W / s, V = J.
+__global__ __launch_bounds__(1024) void bjacobi_finish_kernel(int n, const double* Wt, const double* Jt, double* Uo,
+                                                             double* s, double* Vo, double* sig, int* rank,
+                                                             const int* flags, int* sweeps_out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int p = wave; p < n; p += nw) {
+    double acc = 0.0;
+    for (int i = lane; i < n; i += 64) {
+      const double x = Wt[static_cast<int64_t>(p) * n + i];
+      acc += x * x;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) sig[p] = sqrt(acc);
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    const double sp = sig[p];
+    int rk = 0;
+    for (int q = 0; q < n; ++q) {
+      const double sq = sig[q];
+      rk += (sq > sp || (sq == sp && q < p)) ? 1 : 0;
+    }
+    rank[p] = rk;
+    s[rk] = sp;
+  }
+  __syncthreads();
+  for (int64_t idx = threadIdx.x; idx < static_cast<int64_t>(n) * n; idx += blockDim.x) {
+    const int p = static_cast<int>(idx / n), i = static_cast<int>(idx % n);
+    const int rk = rank[p];
+    const double sp = sig[p];
+    Uo[static_cast<int64_t>(i) * n + rk] = sp > 0.0 ? Wt[idx] / sp : 0.0;
+    Vo[static_cast<int64_t>(i) * n + rk] = Jt[idx];
+  }
+  if (threadIdx.x == 0 && sweeps_out) *sweeps_out = flags[0] ? flags[1 + 64] + 1 : -1;
+}
+
 // ============================================================ Philox Gaussian
 
 __device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
@@ -909,21 +1039,61 @@ void launch_upper_mult(int l, const double* A, const double* B, double* Cm, int6
 }
 
 size_t jacobi_workspace_doubles(int n) {
-  const int np = n + (n & 1);
-  return 2 * static_cast<size_t>(np) * n + 2 * static_cast<size_t>(np) + 8;
+  const int np = static_cast<int>(round_up(n, 32));  // covers the padding of both variants
+  return 2 * static_cast<size_t>(np) * n + 2 * static_cast<size_t>(np) + 96;
 }
 
 void launch_jacobi_svd(int n, const double* A, int64_t lda, double* U, double* s, double* V, double* work,
                        int* sweeps_out, hipStream_t stream) {
   ISVD_CHECK(n >= 1 && n <= kJacobiMaxN, ISVD_E_INVALID, "small svd: n out of range");
-  if (n <= 8 * kJacobiPerLane)
-    hipLaunchKernelGGL(jacobi_kernel<8>, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
-  else if (n <= 16 * kJacobiPerLane)
-    hipLaunchKernelGGL(jacobi_kernel<16>, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
-  else if (n <= 32 * kJacobiPerLane)
-    hipLaunchKernelGGL(jacobi_kernel<32>, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
-  else
-    hipLaunchKernelGGL(jacobi_kernel<64>, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
+  if (n <= 64 || n > 512) {
+    // one workgroup, pairs held in registers
+    if (n <= 8 * kJacobiPerLane)
+      hipLaunchKernelGGL(jacobi_kernel<8>, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
+    else if (n <= 16 * kJacobiPerLane)
+      hipLaunchKernelGGL(jacobi_kernel<16>, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
+    else if (n <= 32 * kJacobiPerLane)
+      hipLaunchKernelGGL(jacobi_kernel<32>, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
+    else
+      hipLaunchKernelGGL(jacobi_kernel<64>, dim3(1), dim3(1024), 0, stream, n, A, lda, U, s, V, work, sweeps_out);
+    ISVD_LAUNCH_CHECK();
+    return;
+  }
+  // block-parallel version: blocks of B columns, an even number of blocks
+  const int B = n <= 304 ? 16 : 8;
+  int nbk = static_cast<int>(ceil_div(n, B));
+  nbk += nbk & 1;
+  const int np = nbk * B;
+  double* Wt = work;
+  double* Jt = Wt + static_cast<int64_t>(np) * n;
+  double* sig = Jt + static_cast<int64_t>(np) * n;
+  int* rank = reinterpret_cast<int*>(sig + n);
+  int* flags = rank + n + 1;
+  const int nflags = 1 + 64 + 2;
+  const int64_t total = static_cast<int64_t>(np) * n;
+  hipLaunchKernelGGL(bjacobi_init_kernel, dim3(static_cast<unsigned>(ceil_div(total, 256))), dim3(256), 0, stream, n, np,
+                     A, lda, Wt, Jt, flags, nflags);
+  ISVD_LAUNCH_CHECK();
+  const size_t lds = static_cast<size_t>(4) * B * n * sizeof(double);
+  constexpr int kMaxSweeps = 40;
+  int done = 0;
+  for (int sweep = 0; sweep < kMaxSweeps && !done; ++sweep) {
+    for (int r = 0; r < nbk - 1; ++r) {
+      if (B == 16)
+        hipLaunchKernelGGL(bjacobi_round_kernel<16>, dim3(nbk / 2), dim3(kBJThreads), lds, stream, n, nbk, r, sweep, Wt, Jt, flags);
+      else
+        hipLaunchKernelGGL(bjacobi_round_kernel<8>, dim3(nbk / 2), dim3(kBJThreads), lds, stream, n, nbk, r, sweep, Wt, Jt, flags);
+    }
+    hipLaunchKernelGGL(bjacobi_check_kernel, dim3(1), dim3(64), 0, stream, sweep, flags);
+    ISVD_LAUNCH_CHECK();
+    // read the convergence flag after the first few sweeps, then every other sweep
+    if (sweep >= 3 && (sweep % 2 == 1)) {
+      ISVD_HIP(hipMemcpyAsync(&done, flags, sizeof(int), hipMemcpyDeviceToHost, stream));
+      ISVD_HIP(hipStreamSynchronize(stream));
+    }
+  }
+  hipLaunchKernelGGL(bjacobi_finish_kernel, dim3(1), dim3(1024), 0, stream, n, Wt, Jt, U, s, V, sig, rank, flags,
+                     sweeps_out);
   ISVD_LAUNCH_CHECK();
 }
 

@@ -41,7 +41,8 @@ struct SvdState {
 // CholeskyQR2 of Y in place; Rout (optional) receives R2 R1; colsum (optional,
 // l doubles) receives 1^T Q of the stored result.
 template <typename T>
-void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* colsum, hipStream_t stream) {
+void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* colsum, hipStream_t stream,
+                    int npass = 2) {
   using C = typename ComputeOf<T>::type;
   const int l = st.l, lp = st.lp;
   st.G.ensure(static_cast<size_t>(l) * l * sizeof(double));
@@ -51,12 +52,12 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* cols
   st.Dc.ensure(static_cast<size_t>(lp) * 16 * sizeof(C));
   st.flag.ensure(4 * sizeof(int));
   st.gram_work.ensure(gram_workspace_doubles(rows, l, l) * sizeof(double));
-  double* Rp[3] = {st.R1.as<double>(), st.R2.as<double>(), nullptr};
-  int passes = 2;
+  double* Rp[2] = {st.R1.as<double>(), st.R2.as<double>()};
+  int passes = npass;
   for (int pass = 0; pass < passes; ++pass) {
     double* Rdst = Rp[pass < 2 ? pass : 1];
-    if (pass == 2) {
-      // third pass after a shifted first pass: fold R2 into R1 first
+    if (pass >= 2) {
+      // a further pass: fold R2 into R1 first (R1 <- R2 R1)
       st.Rtmp.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
       launch_upper_mult(l, st.R2.as<double>(), st.R1.as<double>(), st.Rtmp.as<double>(), lp, stream);
       ISVD_HIP(hipMemcpyAsync(st.R1.p, st.Rtmp.p, static_cast<size_t>(lp) * lp * sizeof(double),
@@ -69,7 +70,8 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* cols
     ISVD_HIP(hipMemcpyAsync(&flag, st.flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
     ISVD_HIP(hipStreamSynchronize(stream));
     if (flag) {
-      // shifted Cholesky QR (Fukaya et al.): G + s I with s ~ 11 (m l + l (l+1)) u tr(G)
+      // shifted Cholesky QR (Fukaya et al.): G + s I with s ~ 11 (m l + l (l+1)) u tr(G);
+      // the shifted pass is followed by two more
       std::vector<double> g(static_cast<size_t>(l) * l);
       double tr = 0.0;
       ISVD_HIP(hipMemcpy(g.data(), st.G.p, g.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -83,14 +85,17 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* cols
       ISVD_CHECK(flag == 0 && tr > 0.0 && std::isfinite(tr), ISVD_E_NOT_SPD,
                  "Cholesky breakdown: Gram matrix not positive definite even with a shift");
       st.fallback = 1;
-      if (passes == 2) passes = 3;
+      passes = pass + 3 > passes ? pass + 3 : passes;
     }
     const bool last = pass + 1 == passes;
     if (last && colsum) st.cs_work.ensure(trsm_colsum_workspace(l) * sizeof(double));
     launch_trsm_tall<T>(rows, l, Y, st.ld, st.Rcc.as<C>(), st.Dc.as<C>(), last ? colsum : nullptr,
                         last && colsum ? st.cs_work.as<double>() : nullptr, stream);
   }
-  if (Rout) launch_upper_mult(l, st.R2.as<double>(), st.R1.as<double>(), Rout, lp, stream);
+  if (Rout) {
+    if (passes == 1) launch_convert<double, double>(lp, lp, st.R1.as<double>(), lp, Rout, lp, stream);
+    else launch_upper_mult(l, st.R2.as<double>(), st.R1.as<double>(), Rout, lp, stream);
+  }
 }
 
 void ritz(SvdState& st, hipStream_t stream) {
@@ -256,12 +261,17 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
       st.iterations = t - 1;
       return 0;
     }
-    orthonormalize<T>(st, Y, st.r, nullptr, ne ? st.sum_r.as<double>() : nullptr, stream);
+    // Rayleigh-Ritz at the end of this iteration needs orthonormal Qr, Qc (CholeskyQR2);
+    // otherwise one Cholesky pass (Algorithm 2) keeps the span, which is all the next product needs
+    const bool ritz_now = fixed ? (t >= prm->q)
+                                : (t >= sched.next || (phase_cap > 0 && t + 1 >= phase_cap) || t + 1 >= prm->max_iter);
+    const int np_ = ritz_now || prm->orth_passes >= 2 ? 2 : 1;
+    orthonormalize<T>(st, Y, st.r, nullptr, ne ? st.sum_r.as<double>() : nullptr, stream, np_);
     std::swap(st.qr.p, st.y.p);
     std::swap(st.qr.bytes, st.y.bytes);
     apply_operator<T>(op, true, st.qr.as<T>(), st.ld, l, st.w.as<T>(), st.ld, stream, ne ? st.sum_r.as<double>() : nullptr);
     st.applies++;
-    orthonormalize<T>(st, st.w.as<T>(), st.c, st.Rc.as<double>(), ne ? st.sum_c.as<double>() : nullptr, stream);
+    orthonormalize<T>(st, st.w.as<T>(), st.c, st.Rc.as<double>(), ne ? st.sum_c.as<double>() : nullptr, stream, np_);
     std::swap(st.qc.p, st.w.p);
     std::swap(st.qc.bytes, st.w.bytes);
     qc_sums = ne;
@@ -271,7 +281,7 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
       st.iterations = t;
       return 1;
     }
-    if (!fixed && (t >= sched.next || (phase_cap > 0 && t + 1 >= phase_cap))) {
+    if (!fixed && ritz_now) {
       ritz(st, stream);
       st.ritz_iter = t;
     }

@@ -46,7 +46,8 @@ class _Design(ct.Structure):
 class _SvdParams(ct.Structure):
     _fields_ = [("k", ct.c_int), ("p", ct.c_int), ("q", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
                 ("check_every", ct.c_int), ("seed", ct.c_uint64), ("omega", ct.c_void_p),
-                ("ld_omega", ct.c_int64), ("fp32_switch_tol", ct.c_double), ("bf16_max_iter", ct.c_int)]
+                ("ld_omega", ct.c_int64), ("fp32_switch_tol", ct.c_double), ("bf16_max_iter", ct.c_int),
+                ("orth_passes", ct.c_int)]
 
 
 class _SvdInfo(ct.Structure):
@@ -189,7 +190,7 @@ class Operator:
         return out
 
     def truncated_svd(self, k, p, q=2, tol=0.0, max_iter=1000, check_every=0, seed=0, omega=None,
-                      fp32_switch_tol=0.0, bf16_max_iter=0, allow_not_converged=False):
+                      fp32_switch_tol=0.0, bf16_max_iter=0, orth_passes=0, allow_not_converged=False):
         """(U, S, V, info) through isvd_truncated_svd."""
         r, c = self.shape
         out_dtype = torch.float32 if self.precision == BF16 else self.dtype
@@ -200,7 +201,7 @@ class Operator:
         prm = _SvdParams(k=k, p=p, q=q, tol=tol, max_iter=max_iter, check_every=check_every, seed=seed,
                          omega=_ptr(omega) if omega is not None else None,
                          ld_omega=_ld(omega) if omega is not None else 0, fp32_switch_tol=fp32_switch_tol,
-                         bf16_max_iter=bf16_max_iter)
+                         bf16_max_iter=bf16_max_iter, orth_passes=orth_passes)
         if omega is not None:
             assert omega.dtype == self.dtype and omega.shape == (c, k + p)
         info = _SvdInfo()

@@ -165,7 +165,8 @@ def main():
         times.append(time.perf_counter() - ts)
         infos.append(info)
         print(f"[bench] step {s}: {times[-1]:.3f} s, iterations {info.iterations}, applies {info.applies}, "
-              f"rho {info.residual:.2e}, status {info.status}, ritz {info.ritz_steps}, sweeps {info.jacobi_sweeps}",
+              f"rho {info.residual:.2e}, status {info.status}, ritz {info.ritz_steps}, sweeps {info.jacobi_sweeps}, "
+              f"bf16 iterations {info.bf16_iterations}, fallback {info.used_fallback}",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
@@ -207,6 +208,7 @@ def main():
         "config": {"workload": cfg.name, "n": g.n, "nnz": int(g.nnz), "k": cfg.k, "p": cfg.p,
                    "K": cfg.K, "lambda": cfg.lam, "tol": args.tol,
                    "iterations": [i.iterations for i in infos], "applies": [i.applies for i in infos],
+                   **({"bf16_iterations": [i.bf16_iterations for i in infos]} if precision == lib.BF16 else {}),
                    "residual": [i.residual for i in infos], "converged": converged,
                    "median_step_s": round(statistics.median(times), 4),
                    "start_block": "learned warm start" if ws is not None else "gaussian",
@@ -222,8 +224,8 @@ def main():
     if not args.no_cpu_baseline and cfg.n <= 500_000:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         last = infos[-1]
-        orths = 2 * 2 * (last.iterations + 1)
-        line["cpu_baseline"] = cpu_baseline(g, cfg, last.applies, orths)
+        # the oracle orthonormalises every product once (Householder QR)
+        line["cpu_baseline"] = cpu_baseline(g, cfg, last.applies, last.applies)
     op.close()
     print(json.dumps(line), flush=True)
 

@@ -267,13 +267,12 @@ isvd_status isvd_ws_forward(isvd_warmstart* ws, int64_t n, const float* F, float
                             void* stream);
 
 /* Loss and parameter gradient for one graph: forward, subspace loss
- * L = tr(G^-1 Z^T (I - V V^T) Z) / k, G = Z^T Z + mu I, mu = 1e-3 tr(Z^T Z)/k
- * (a ridge held constant in the gradient; mu = 0 would give the mean sin^2 of
- * the principal angles) against orthonormal V (n x k, ld ldv, FP32 device),
- * backward.  grad_out: optional host array of isvd_ws_num_params floats.
- * loss_out: host.  If lr > 0 an Adam step (beta1 0.9, beta2 0.999, eps 1e-8)
- * is applied.  ISVD_E_NOT_SPD (and no update) if G is not positive definite.
- * Synchronises. */
+ * L = tr((Z^T Z)^-1 Z^T (I - V V^T) Z) / k (the mean sin^2 of the principal
+ * angles between span(Z) and span(V)) against orthonormal V (n x k, ld ldv,
+ * FP32 device), backward.  grad_out: optional host array of
+ * isvd_ws_num_params floats.  loss_out: host.  If lr > 0 an Adam step
+ * (beta1 0.9, beta2 0.999, eps 1e-8) is applied.  ISVD_E_NOT_SPD, and no
+ * parameter update, if Z^T Z is not positive definite.  Synchronises. */
 isvd_status isvd_ws_train_step(isvd_warmstart* ws, int64_t n, const float* F, const float* V,
                                int64_t ldv, double lr, double* loss_out, float* grad_out,
                                void* stream);

@@ -15,14 +15,10 @@ features (16 per node, for M's column side):
     used: T is row-stochastic, so it is all ones.
 network:  Z = GELU(GELU(F W1 + b1) W2 + b2) W3 + b3,  16 -> 128 -> 128 -> k,
           GELU(x) = x Phi(x) with the exact normal CDF.
-loss:     L(Z) = tr(G^-1 Z^T (I - V V^T) Z) / k for orthonormal V (n x k)
-          with G = Z^T Z + mu I.  With mu = 0 it is the mean squared sine of
-          the principal angles between span(Z) and span(V), invariant to
-          Z -> Z R for invertible R.  Training uses the ridge
-          mu = mu_rel tr(Z^T Z) / k (mu_rel = 1e-3), held constant when
-          differentiating, which keeps G^-1 bounded if Z loses column rank.
-gradient: dL/dZ = (2/k) ((I - V V^T) Z G^-1 - Z G^-1 Z^T (I - V V^T) Z G^-1),
-          which is (2/k)(I - Z G^-1 Z^T)(I - V V^T) Z G^-1 when mu = 0.
+loss:     L(Z) = tr((Z^T Z)^-1 Z^T (I - V V^T) Z) / k for orthonormal V
+          (n x k): the mean squared sine of the principal angles between
+          span(Z) and span(V); invariant to Z -> Z R for invertible R.
+gradient: dL/dZ = (2/k) (I - Z G^-1 Z^T)(I - V V^T) Z G^-1, G = Z^T Z.
 """
 
 from __future__ import annotations
@@ -100,13 +96,11 @@ def forward(params, f):
     return z, (f, h1p, h1, h2p, h2)
 
 
-def subspace_loss(z, v, mu_rel=0.0):
-    """(loss, dL/dZ) for the subspace loss against orthonormal v (see the
-    module docstring; mu_rel = 0 gives the plain loss)."""
+def subspace_loss(z, v):
+    """(loss, dL/dZ) for the subspace loss against orthonormal v."""
     k = z.shape[1]
     g = z.T @ z
-    mu = mu_rel * np.trace(g) / k
-    ginv = np.linalg.inv(g + mu * np.eye(k))
+    ginv = np.linalg.inv(g)
     pz = z - v @ (v.T @ z)                        # (I - V V^T) Z
     loss = np.trace(ginv @ (z.T @ pz)) / k
     x = pz @ ginv                                 # (I - V V^T) Z G^-1

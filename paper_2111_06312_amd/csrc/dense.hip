@@ -8,6 +8,9 @@
 // measured on gfx950).
 #include "dense.h"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace isvd {
 
 namespace {
@@ -30,102 +33,203 @@ template <typename C, typename T>
 __device__ inline C ld_as(const T* p) { return static_cast<C>(Elem<T>::load(p)); }
 
 // ============================================================ Gram
+//
+// C = A^T B over a tall row range with exact products and FP64 sums (FP64
+// MFMA 16x16x4).  The 16 x 16 output tiles are grouped in 3 x 3 blocks; each
+// wave owns one block ("job") and keeps its nine accumulators in registers,
+// so one k-step reads three A and three B fragments for up to nine MFMAs.
+// For A^T A only blocks on or above the diagonal exist and tiles below the
+// diagonal inside a diagonal block are skipped.  A workgroup holds up to 16
+// waves (jobs) and streams one row slice through two LDS buffers (rows staged
+// as FP32 for FP32/BF16 inputs, FP64 otherwise): the next chunk is loaded
+// into registers while the MFMAs of the current one run, one barrier per
+// chunk.  Row slices write partial tiles that a second kernel adds in a
+// fixed order.
 
-constexpr int kGramWaves = 8;
-constexpr int kGramThreads = 64 * kGramWaves;
-constexpr int kGramMaxTPW = 12;      // tiles per wave of the largest instantiation
-constexpr int kGramPrefetch = 16;    // staged elements per thread per row chunk
+constexpr int kGramRB = 3;          // tiles per job side
+constexpr int kGramMaxWaves = 16;
+constexpr int kGramPF = 16;         // staged elements per thread per chunk
 constexpr int kGramMaxParts = 256;
+constexpr size_t kGramMaxLds = 96 * 1024;
 
-__device__ inline void decode_tile(int idx, bool same, int tm, int tp, int& ti, int& tj) {
-  if (same) {
-    int i = 0;
-    while (idx >= tm - i) {
-      idx -= tm - i;
-      ++i;
+template <typename TA, typename TB>
+struct GramStage {
+  using type = typename std::conditional<std::is_same<TA, double>::value || std::is_same<TB, double>::value,
+                                         double, float>::type;
+};
+
+// LDS row stride (elements) for `cols` staged columns: consecutive rows start
+// 64 bytes apart modulo 256, so the four k-rows of one fragment read fall in
+// different banks.
+__host__ __device__ inline int gram_lds_ld(int cols, int esize) {
+  const int bytes = cols * esize;
+  const int pad = ((64 - bytes) % 256 + 256) % 256;
+  return (bytes + pad) / esize;
+}
+
+// The k-steps of one chunk for one job (a 3 x 3 block of tiles; on a
+// diagonal block of A^T A the tiles below its diagonal are skipped).  The
+// fragments of the next k-step are read while the MFMAs of the current one run.
+template <typename S>
+__device__ inline void gram_ksteps(const S* As, const S* Bs, int lda_s, int ldb_s, int nk, int ti0, int tj0, int li,
+                                   int lk, bool diag, v4d (&acc)[kGramRB][kGramRB]) {
+  const S* pa = As + lk * lda_s + ti0 * 16 + li;
+  const S* pb = Bs + lk * ldb_s + tj0 * 16 + li;
+  S fa[kGramRB], fb[kGramRB];
+#pragma unroll
+  for (int r = 0; r < kGramRB; ++r) {
+    fa[r] = pa[r * 16];
+    fb[r] = pb[r * 16];
+  }
+  for (int kk = 0; kk < nk; ++kk) {
+    double a[kGramRB], b[kGramRB];
+#pragma unroll
+    for (int r = 0; r < kGramRB; ++r) {
+      a[r] = static_cast<double>(fa[r]);
+      b[r] = static_cast<double>(fb[r]);
     }
-    ti = i;
-    tj = i + idx;
-  } else {
-    ti = idx / tp;
-    tj = idx % tp;
+    // next k-step (the last iteration re-reads its own rows: in bounds, unused)
+    const int step = kk + 1 < nk ? 4 : 0;
+    pa += step * lda_s;
+    pb += step * ldb_s;
+#pragma unroll
+    for (int r = 0; r < kGramRB; ++r) {
+      fa[r] = pa[r * 16];
+      fb[r] = pb[r * 16];
+    }
+#pragma unroll
+    for (int r = 0; r < kGramRB; ++r)
+#pragma unroll
+      for (int c = 0; c < kGramRB; ++c)
+        if (r <= c) acc[r][c] = mfma4(a[r], b[c], acc[r][c]);
+    if (!diag) {
+#pragma unroll
+      for (int r = 1; r < kGramRB; ++r)
+#pragma unroll
+        for (int c = 0; c < r; ++c) acc[r][c] = mfma4(a[r], b[c], acc[r][c]);
+    }
   }
 }
 
-// Partial A^T B over one row slice per blockIdx.x, for the 16 x 16 output tiles
-// of group blockIdx.y.  Row chunks of rb rows are staged in LDS as FP64; the
-// next chunk is loaded into registers while the MFMAs of the current one run.
-template <typename TA, typename TB, int TPW>
-__global__ __launch_bounds__(kGramThreads) void gram_partial_kernel(int64_t rows, int m, int p, const TA* A,
-                                                                    int64_t lda, const TB* B, int64_t ldb,
-                                                                    int same, int tm, int tp, int ntiles,
-                                                                    int tiles_per_group, int64_t rows_per_block,
-                                                                    int rb, double* partial, int mp, int pp) {
-  using PF = typename ComputeOf<TA>::type;
-  extern __shared__ double gsm[];
-  double* As = gsm;
-  double* Bs = same ? gsm : gsm + rb * mp;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Rows staged per wave and chunk: J rows of CS 64-column steps each (for A
+// and, if B differs, for B).
+template <typename S, int CS, bool SAME>
+constexpr int gram_rows_per_wave() {
+  constexpr int words = CS * static_cast<int>(sizeof(S) / 4) * (SAME ? 1 : 2);
+  return kGramPF / words > 0 ? kGramPF / words : 1;
+}
+
+template <typename TA, typename TB, int CS, bool SAME>
+__global__ __launch_bounds__(64 * kGramMaxWaves) void gram_partial_kernel(
+    int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb, int tm, int tp, int nbi,
+    int nbj, int njobs, int64_t rows_per_block, int rb, int ldsa, int ldsb, double* partial, int mp, int pp) {
+  using S = typename GramStage<TA, TB>::type;
+  constexpr int J = gram_rows_per_wave<S, CS, SAME>();
+  extern __shared__ __align__(16) unsigned char gram_smem[];
+  S* buf0 = reinterpret_cast<S*>(gram_smem);
+  const int per_buf = rb * (ldsa + (SAME ? 0 : ldsb));
+  const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int gfirst = blockIdx.y * tiles_per_group;
-  const int glast = min(ntiles, gfirst + tiles_per_group);
-  int ti[TPW], tj[TPW];
-  bool act[TPW];
-  v4d acc[TPW];
-#pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    // surplus slots recompute the group's last tile (no branch around the
-    // MFMAs) and are not stored
-    const int idx = gfirst + wave + kGramWaves * t;
-    act[t] = idx < glast;
-    decode_tile(act[t] ? idx : glast - 1, same, tm, tp, ti[t], tj[t]);
-    acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int nw = static_cast<int>(blockDim.x >> 6);
+  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int job = static_cast<int>(blockIdx.y) * nw + wv;
+  const bool has_job = job < njobs;
+  // job -> block (bi, bj): upper triangle row by row for A^T A, else row-major
+  int bi = 0, bj = 0;
+  if (has_job) {
+    if (SAME) {
+      int rest = job;
+      while (rest >= nbj - bi) {
+        rest -= nbj - bi;
+        ++bi;
+      }
+      bj = bi + rest;
+    } else {
+      bi = job / nbj;
+      bj = job - bi * nbj;
+    }
   }
+  const int ti0 = kGramRB * bi, tj0 = kGramRB * bj;
+  const int mpa = 16 * kGramRB * nbi, ppa = 16 * kGramRB * nbj;   // staged columns: whole blocks
+  // Staged columns run to whole blocks (zeros past m and p), so edge blocks
+  // are full blocks whose outer tiles are not stored.
+  const bool diag = SAME && bi == bj;
+  v4d acc[kGramRB][kGramRB];
+#pragma unroll
+  for (int r = 0; r < kGramRB; ++r)
+#pragma unroll
+    for (int c = 0; c < kGramRB; ++c) acc[r][c] = v4d{0.0, 0.0, 0.0, 0.0};
+
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
-  const int na = rb * mp, nb = same ? 0 : rb * pp;
-  PF pf[kGramPrefetch];
+  // wave wv stages chunk rows wv, wv + nw, ...; lane owns columns lane + 64 s
+  S pa[J][CS];
+  S pb[SAME ? 1 : J][SAME ? 1 : CS];
   auto fetch = [&](int64_t base) {
+    const TA* a0 = A + (base + wv) * lda + lane;
+    const TB* b0 = B + (base + wv) * ldb + lane;
 #pragma unroll
-    for (int i = 0; i < kGramPrefetch; ++i) {
-      const int f = threadIdx.x + kGramThreads * i;
-      PF v = PF(0);
-      if (f < na) {
-        const int r = f / mp, c = f - r * mp;
-        const int64_t row = base + r;
-        if (row < r1 && c < m) v = static_cast<PF>(Elem<TA>::load(A + row * lda + c));
-      } else if (f < na + nb) {
-        const int g = f - na, r = g / pp, c = g - r * pp;
-        const int64_t row = base + r;
-        if (row < r1 && c < p) v = static_cast<PF>(Elem<TB>::load(B + row * ldb + c));
+    for (int j = 0; j < J; ++j) {
+      const int rl = wv + nw * j;
+      const bool ok = rl < rb && base + rl < r1;   // wave-uniform
+      const TA* aj = a0 + static_cast<int64_t>(nw * j) * lda;
+#pragma unroll
+      for (int s = 0; s < CS; ++s)
+        pa[j][s] = (ok && lane + 64 * s < m) ? static_cast<S>(Elem<TA>::load(aj + 64 * s)) : S(0);
+      if constexpr (!SAME) {
+        const TB* bj_ = b0 + static_cast<int64_t>(nw * j) * ldb;
+#pragma unroll
+        for (int s = 0; s < CS; ++s)
+          pb[j][s] = (ok && lane + 64 * s < p) ? static_cast<S>(Elem<TB>::load(bj_ + 64 * s)) : S(0);
       }
-      pf[i] = v;
     }
   };
-  if (r0 < r1) fetch(r0);
-  for (int64_t base = r0; base < r1; base += rb) {
-    __syncthreads();
+  auto stage = [&](S* dst) {
 #pragma unroll
-    for (int i = 0; i < kGramPrefetch; ++i) {
-      const int f = threadIdx.x + kGramThreads * i;
-      if (f < na + nb) gsm[f] = static_cast<double>(pf[i]);
-    }
-    __syncthreads();
-    if (base + rb < r1) fetch(base + rb);
-    for (int kk = 0; kk < rb / 4; ++kk) {
-      const int kr = kk * 4 + lk;
+    for (int j = 0; j < J; ++j) {
+      const int rl = wv + nw * j;
+      if (rl >= rb) continue;
+      S* da = dst + rl * ldsa + lane;
 #pragma unroll
-      for (int t = 0; t < TPW; ++t) acc[t] = mfma4(As[kr * mp + ti[t] * 16 + li], Bs[kr * pp + tj[t] * 16 + li], acc[t]);
+      for (int s = 0; s < CS; ++s)
+        if (lane + 64 * s < mpa) da[64 * s] = pa[j][s];
+      if constexpr (!SAME) {
+        S* db = dst + rb * ldsa + rl * ldsb + lane;
+#pragma unroll
+        for (int s = 0; s < CS; ++s)
+          if (lane + 64 * s < ppa) db[64 * s] = pb[j][s];
+      }
     }
+  };
+  if (r0 < r1) {
+    fetch(r0);
+    stage(buf0);
   }
+  __syncthreads();
+  int cur = 0;
+  for (int64_t base = r0; base < r1; base += rb) {
+    const bool more = base + rb < r1;
+    if (more) fetch(base + rb);
+    const S* As = buf0 + cur * per_buf;
+    const S* Bs = SAME ? As : As + rb * ldsa;
+    const int ldb_s = SAME ? ldsa : ldsb;
+    if (has_job) gram_ksteps(As, Bs, ldsa, ldb_s, rb / 4, ti0, tj0, li, lk, diag, acc);
+    if (more) stage(buf0 + (cur ^ 1) * per_buf);
+    __syncthreads();
+    cur ^= 1;
+  }
+  if (!has_job) return;
   double* part = partial + static_cast<int64_t>(blockIdx.x) * mp * pp;
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    if (!act[t]) continue;
+  for (int r = 0; r < kGramRB; ++r)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      part[static_cast<int64_t>(ti[t] * 16 + drow<double>(lk, r)) * pp + tj[t] * 16 + li] = acc[t][r];
-  }
+    for (int c = 0; c < kGramRB; ++c) {
+      const int ti = ti0 + r, tj = tj0 + c;
+      if (ti >= tm || tj >= tp || (SAME && ti > tj)) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        part[static_cast<int64_t>(ti * 16 + drow<double>(lk, q)) * pp + tj * 16 + li] = acc[r][c][q];
+    }
 }
 
 // C[a][b] = sum over row slices of the partial Gram tiles: 64 outputs per
@@ -153,50 +257,89 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int npar
 }
 
 struct GramPlan {
-  int mp, pp, tm, tp, ntiles, rb, nparts, groups, tpg, tpw;
+  int mp, pp, tm, tp, nbi, nbj, njobs, waves, groups, cs, rb, ldsa, ldsb, nparts;
   int64_t rows_per_block;
   size_t lds;
 };
 
-GramPlan plan_gram(int64_t rows, int m, int p, bool same) {
+// Row slices: at most kGramMaxParts, each a multiple of 64 rows.
+int64_t gram_rows_per_part(int64_t rows) {
+  const int64_t want = ceil_div(rows > 0 ? rows : 1, kGramMaxParts);
+  return round_up(want < 64 ? 64 : want, 64);
+}
+
+constexpr int kGramCS[] = {1, 2, 3, 4, 5, 6, 8, 16, 32};
+
+GramPlan plan_gram(int64_t rows, int m, int p, bool same, int esize) {
   GramPlan g;
   g.mp = pad16(m);
   g.pp = pad16(p);
   g.tm = g.mp / 16;
   g.tp = g.pp / 16;
-  g.ntiles = same ? g.tm * (g.tm + 1) / 2 : g.tm * g.tp;
-  const int cols = g.mp + (same ? 0 : g.pp);
-  g.rb = 32;
-  while (g.rb > 4 && (g.rb * cols > kGramThreads * kGramPrefetch ||
-                      static_cast<size_t>(g.rb) * cols * 8 > 96 * 1024))
-    g.rb /= 2;
-  ISVD_CHECK(g.rb * cols <= kGramThreads * kGramPrefetch, ISVD_E_INVALID, "gram: block too wide");
-  g.lds = static_cast<size_t>(g.rb) * cols * 8;
-  g.groups = static_cast<int>(ceil_div(g.ntiles, kGramWaves * kGramMaxTPW));
-  g.tpg = static_cast<int>(ceil_div(g.ntiles, g.groups));
-  g.tpw = static_cast<int>(ceil_div(g.tpg, kGramWaves));
-  const int64_t want = ceil_div(rows > 0 ? rows : 1, kGramMaxParts);
-  g.rows_per_block = round_up(want < 64 ? 64 : want, 32);
+  g.nbi = static_cast<int>(ceil_div(g.tm, kGramRB));
+  g.nbj = static_cast<int>(ceil_div(g.tp, kGramRB));
+  g.njobs = same ? g.nbi * (g.nbi + 1) / 2 : g.nbi * g.nbj;
+  g.groups = static_cast<int>(ceil_div(g.njobs, kGramMaxWaves));
+  g.waves = static_cast<int>(ceil_div(g.njobs, g.groups));
+  const int mpa = 16 * kGramRB * g.nbi, ppa = 16 * kGramRB * g.nbj;   // staged columns: whole blocks
+  const int need = static_cast<int>(ceil_div(same ? mpa : std::max(mpa, ppa), 64));
+  g.cs = 0;
+  for (int c : kGramCS)
+    if (c >= need) {
+      g.cs = c;
+      break;
+    }
+  ISVD_CHECK(g.cs > 0, ISVD_E_INVALID, "gram: more than 2048 columns");
+  const int words = g.cs * esize / 4 * (same ? 1 : 2);
+  const int J = kGramPF / words > 0 ? kGramPF / words : 1;
+  if (g.waves * J < 4) g.waves = static_cast<int>(ceil_div(4, J));   // at least one k-step per chunk
+  g.ldsa = gram_lds_ld(mpa, esize);
+  g.ldsb = same ? 0 : gram_lds_ld(ppa, esize);
+  g.rb = (g.waves * J) / 4 * 4;
+  if (g.rb > 64) g.rb = 64;
+  while (g.rb > 4 && static_cast<size_t>(2) * g.rb * (g.ldsa + g.ldsb) * esize > kGramMaxLds) g.rb -= 4;
+  ISVD_CHECK(static_cast<size_t>(2) * g.rb * (g.ldsa + g.ldsb) * esize <= kGramMaxLds, ISVD_E_INVALID,
+             "gram: block too wide");
+  g.lds = static_cast<size_t>(2) * g.rb * (g.ldsa + g.ldsb) * esize;
+  g.rows_per_block = gram_rows_per_part(rows);
   g.nparts = static_cast<int>(ceil_div(rows > 0 ? rows : 1, g.rows_per_block));
   return g;
 }
 
-template <typename TA, typename TB, int TPW>
+template <typename TA, typename TB, int CS, bool SAME>
 void gram_launch(const GramPlan& g, int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
-                 bool same, double* work, hipStream_t stream) {
-  hipLaunchKernelGGL((gram_partial_kernel<TA, TB, TPW>), dim3(g.nparts, g.groups), dim3(kGramThreads), g.lds,
-                     stream, rows, m, p, A, lda, B, ldb, same ? 1 : 0, g.tm, g.tp, g.ntiles, g.tpg,
-                     g.rows_per_block, g.rb, work, g.mp, g.pp);
+                 double* work, hipStream_t stream) {
+  hipLaunchKernelGGL((gram_partial_kernel<TA, TB, CS, SAME>), dim3(g.nparts, g.groups), dim3(64 * g.waves), g.lds,
+                     stream, rows, m, p, A, lda, B, ldb, g.tm, g.tp, g.nbi, g.nbj, g.njobs, g.rows_per_block, g.rb,
+                     g.ldsa, g.ldsb, work, g.mp, g.pp);
   ISVD_LAUNCH_CHECK();
+}
+
+template <typename TA, typename TB, int CS>
+void gram_launch_cs(const GramPlan& g, int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B,
+                    int64_t ldb, bool same, double* work, hipStream_t stream) {
+  if constexpr (std::is_same<TA, TB>::value) {
+    if (same) return gram_launch<TA, TB, CS, true>(g, rows, m, p, A, lda, B, ldb, work, stream);
+  }
+  gram_launch<TA, TB, CS, false>(g, rows, m, p, A, lda, B, ldb, work, stream);
 }
 
 template <typename TA, typename TB>
 void gram_impl(int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
                bool same, double* C, int64_t ldc, double* work, hipStream_t stream) {
-  const GramPlan g = plan_gram(rows, m, p, same);
-  if (g.tpw <= 4) gram_launch<TA, TB, 4>(g, rows, m, p, A, lda, B, ldb, same, work, stream);
-  else if (g.tpw <= 8) gram_launch<TA, TB, 8>(g, rows, m, p, A, lda, B, ldb, same, work, stream);
-  else gram_launch<TA, TB, kGramMaxTPW>(g, rows, m, p, A, lda, B, ldb, same, work, stream);
+  using S = typename GramStage<TA, TB>::type;
+  const GramPlan g = plan_gram(rows, m, p, same, static_cast<int>(sizeof(S)));
+  switch (g.cs) {
+    case 1: gram_launch_cs<TA, TB, 1>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+    case 2: gram_launch_cs<TA, TB, 2>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+    case 3: gram_launch_cs<TA, TB, 3>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+    case 4: gram_launch_cs<TA, TB, 4>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+    case 5: gram_launch_cs<TA, TB, 5>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+    case 6: gram_launch_cs<TA, TB, 6>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+    case 8: gram_launch_cs<TA, TB, 8>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+    case 16: gram_launch_cs<TA, TB, 16>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+    default: gram_launch_cs<TA, TB, 32>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+  }
   const int64_t total = static_cast<int64_t>(m) * p;
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(total, 64))), dim3(256),
                      0, stream, m, p, g.nparts, work, g.mp, g.pp, same ? 1 : 0, C, ldc);
@@ -941,8 +1084,8 @@ __global__ void small_residual_kernel(int l, int k, const double* Rc, int64_t ld
 // ============================================================ host wrappers
 
 size_t gram_workspace_doubles(int64_t rows, int m, int p) {
-  const GramPlan g = plan_gram(rows, m, p, false);
-  return static_cast<size_t>(g.nparts) * g.mp * g.pp;
+  const int64_t nparts = ceil_div(rows > 0 ? rows : 1, gram_rows_per_part(rows));
+  return static_cast<size_t>(nparts) * pad16(m) * pad16(p);
 }
 
 template <typename T>

@@ -16,6 +16,9 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+// Gathers in flight per lane group.  Loads stay in their 16-byte storage form
+// until their FMAs, so the registers (and the occupancy) do not grow with
+// the unpacked width; deeper unrolling measured slower (fewer waves per SIMD).
 constexpr int kUnroll = 4;
 
 // 16-byte chunk (VEC) or single-element access to a storage row.
@@ -23,6 +26,9 @@ template <typename T, typename C, bool VEC> struct Chunk;
 
 template <typename T, typename C> struct Chunk<T, C, false> {
   static constexpr int N = 1;
+  using Raw = C;
+  __device__ static inline Raw load_raw(const T* p) { return static_cast<C>(Elem<T>::load(p)); }
+  __device__ static inline void unpack(const Raw& r, C (&x)[N]) { x[0] = r; }
   __device__ static inline void load(const T* p, C (&x)[N]) { x[0] = static_cast<C>(Elem<T>::load(p)); }
   __device__ static inline void store(T* p, const C (&x)[N], int valid) {
     if (valid > 0) Elem<T>::store(p, x[0]);
@@ -31,6 +37,11 @@ template <typename T, typename C> struct Chunk<T, C, false> {
 
 template <> struct Chunk<float, float, true> {
   static constexpr int N = 4;
+  using Raw = float4;
+  __device__ static inline Raw load_raw(const float* p) { return *reinterpret_cast<const float4*>(p); }
+  __device__ static inline void unpack(const Raw& v, float (&x)[N]) {
+    x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+  }
   __device__ static inline void load(const float* p, float (&x)[N]) {
     float4 v = *reinterpret_cast<const float4*>(p);
     x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
@@ -46,6 +57,9 @@ template <> struct Chunk<float, float, true> {
 
 template <> struct Chunk<double, double, true> {
   static constexpr int N = 2;
+  using Raw = double2;
+  __device__ static inline Raw load_raw(const double* p) { return *reinterpret_cast<const double2*>(p); }
+  __device__ static inline void unpack(const Raw& v, double (&x)[N]) { x[0] = v.x; x[1] = v.y; }
   __device__ static inline void load(const double* p, double (&x)[N]) {
     double2 v = *reinterpret_cast<const double2*>(p);
     x[0] = v.x; x[1] = v.y;
@@ -61,15 +75,17 @@ template <> struct Chunk<double, double, true> {
 
 template <> struct Chunk<bf16, float, true> {
   static constexpr int N = 8;
-  __device__ static inline void load(const bf16* p, float (&x)[N]) {
-    uint4 v = *reinterpret_cast<const uint4*>(p);
-    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  using Raw = uint4;
+  __device__ static inline Raw load_raw(const bf16* p) { return *reinterpret_cast<const uint4*>(p); }
+  __device__ static inline void unpack(const Raw& v, float (&x)[N]) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       x[2 * t] = bf16_to_float(static_cast<uint16_t>(w[t] & 0xffffu));
       x[2 * t + 1] = bf16_to_float(static_cast<uint16_t>(w[t] >> 16));
     }
   }
+  __device__ static inline void load(const bf16* p, float (&x)[N]) { unpack(load_raw(p), x); }
   __device__ static inline void store(bf16* p, const float (&x)[N], int valid) {
     if (valid >= N) {
       uint32_t w[4];
@@ -113,6 +129,7 @@ __device__ inline void accumulate(const SpmmPass& p, int64_t beg, int64_t end, i
                                   int gbase, int nchunks, C (&acc)[NV][Chunk<T, C, VEC>::N]) {
   using CK = Chunk<T, C, VEC>;
   constexpr int EPC = CK::N;
+  constexpr int U = kUnroll;
   const T* src = static_cast<const T*>(p.src);
   const int64_t lds = p.ld_src;
   const C* cscale = static_cast<const C*>(p.colscale);
@@ -131,27 +148,32 @@ __device__ inline void accumulate(const SpmmPass& p, int64_t beg, int64_t end, i
       if (cscale) myg *= csa * cscale[myj] + csb;
     }
     int e = 0;
-    for (; e + kUnroll <= cnt; e += kUnroll) {
-      int j[kUnroll];
-      C g[kUnroll];
+    for (; e + U <= cnt; e += U) {
+      int j[U];
+      C g[U];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
+      for (int u = 0; u < U; ++u) {
         j[u] = bcast_i<G>(myj, gbase + e + u);
         g[u] = bcast_f<G>(myg, gbase + e + u);
       }
-      C x[kUnroll][NV][EPC];
+      // every gather of the batch is issued before the first is consumed; the
+      // data stays in its storage form (one 16-byte chunk) until its FMAs
+      typename CK::Raw x[U][NV];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-        for (int m = 0; m < NV; ++m)
-          if (own[m]) CK::load(src + static_cast<int64_t>(j[u]) * lds + (gl + G * m) * EPC, x[u][m]);
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
+      for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int m = 0; m < NV; ++m)
-          if (own[m])
+          if (own[m]) x[u][m] = CK::load_raw(src + static_cast<int64_t>(j[u]) * lds + (gl + G * m) * EPC);
 #pragma unroll
-            for (int t = 0; t < EPC; ++t) acc[m][t] += g[u] * x[u][m][t];
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int m = 0; m < NV; ++m)
+          if (own[m]) {
+            C v[EPC];
+            CK::unpack(x[u][m], v);
+#pragma unroll
+            for (int t = 0; t < EPC; ++t) acc[m][t] += g[u] * v[t];
+          }
     }
     for (; e < cnt; ++e) {
       const int j = bcast_i<G>(myj, gbase + e);

@@ -3,12 +3,10 @@
 // vectors, its backward pass and Adam.  The network's output replaces the
 // first k columns of Algorithm 1's Gaussian start block.
 //
-// Loss (with mu = 0 sign-, rotation- and scale-invariant: the mean sin^2 of
-// the principal angles between span(Z) and span(V)):
-//   L = tr(G^-1 Z^T (I - V V^T) Z) / k,  G = Z^T Z + mu I,  C = Z^T V,  P = G^-1 C
-//     = 1 - (mu tr(G^-1) + tr(P C^T)) / k,
-//   dL/dZ = (2/k) (Z (P P^T + mu G^-2) - V P^T)   (mu held constant),
-// with the ridge mu = 1e-3 tr(Z^T Z) / k keeping G^-1 bounded.
+// Loss (sign-, rotation- and scale-invariant; mean sin^2 of the principal
+// angles between span(Z) and span(V)):
+//   L = tr((Z^T Z)^-1 Z^T (I - V V^T) Z) / k = 1 - tr(G^-1 C C^T) / k,
+//   G = Z^T Z, C = Z^T V,  dL/dZ = (2/k) (Z P P^T - V P^T),  P = G^-1 C.
 #include <vector>
 
 #include "operator.h"
@@ -28,7 +26,6 @@ namespace isvd {
 namespace {
 
 constexpr int kIn = 16, kHid = 128;
-constexpr double kRidge = 1e-3;  // mu = kRidge tr(Z^T Z) / k
 
 // parameter offsets (floats) in theta: W1 16x128, b1, W2 128x128, b2, W3 128xk, b3
 struct Layout {
@@ -156,28 +153,10 @@ __global__ void adam_kernel(int64_t total, float* theta, const float* g, float* 
 
 // ---------------------------------------------------------------- small FP64 helpers (k x k)
 
-// mu = mu_rel tr(G) / k added to the diagonal of G (k x k, in place); mu kept in *mu_out.
-__global__ void ridge_kernel(int k, double mu_rel, double* G, double* mu_out) {
+// P = Ginv C, PPt = P P^T, loss terms; one workgroup (k <= 512).
+__global__ void loss_small_kernel(int k, const double* Ginv, const double* C, double* P, double* PPt,
+                                  double* loss_out) {
   __shared__ double red[256];
-  double t = 0.0;
-  for (int i = threadIdx.x; i < k; i += blockDim.x) t += G[i * k + i];
-  red[threadIdx.x] = t;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double mu = mu_rel * red[0] / k;
-  __syncthreads();
-  for (int i = threadIdx.x; i < k; i += blockDim.x) G[i * k + i] += mu;
-  if (threadIdx.x == 0) *mu_out = mu;
-}
-
-// P = Ginv C, PPt = P P^T + mu Ginv^2, loss; one workgroup (k <= 512).
-__global__ void loss_small_kernel(int k, const double* Ginv, const double* C, const double* mu_p, double* P,
-                                  double* PPt, double* loss_out) {
-  __shared__ double red[256];
-  const double mu = *mu_p;
   for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
     const int i = idx / k, j = idx % k;
     double s = 0.0;
@@ -188,14 +167,10 @@ __global__ void loss_small_kernel(int k, const double* Ginv, const double* C, co
   double tr = 0.0;
   for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
     const int i = idx / k, j = idx % k;
-    double s = 0.0, q = 0.0;
-    for (int t = 0; t < k; ++t) {
-      s += P[i * k + t] * P[j * k + t];
-      q += Ginv[i * k + t] * Ginv[t * k + j];
-    }
-    PPt[idx] = s + mu * q;
-    tr += P[idx] * C[idx];                 // tr(P C^T) = sum_ij P_ij C_ij
-    if (i == j) tr += mu * Ginv[idx];      // mu tr(G^-1)
+    double s = 0.0;
+    for (int t = 0; t < k; ++t) s += P[i * k + t] * P[j * k + t];
+    PPt[idx] = s;
+    tr += P[idx] * C[idx];   // tr(P C^T) = sum_ij P_ij C_ij
   }
   red[threadIdx.x] = tr;
   __syncthreads();
@@ -400,7 +375,7 @@ void ws_train_step(isvd_warmstart* ws, int64_t n, const float* F, const float* V
   double* Ginv = Dc + static_cast<int64_t>(lp) * 16;
   double* P = Ginv + static_cast<int64_t>(lp) * lp;
   double* PPt = P + static_cast<int64_t>(lp) * lp;
-  double* loss_d = PPt + static_cast<int64_t>(lp) * lp;   // loss, mu
+  double* loss_d = PPt + static_cast<int64_t>(lp) * lp;
   int* flag = reinterpret_cast<int*>(loss_d + 2);
   const size_t gw = gram_workspace_doubles(n, k, k);
   size_t wneed = gw;
@@ -413,9 +388,6 @@ void ws_train_step(isvd_warmstart* ws, int64_t n, const float* F, const float* V
   launch_gram<float>(n, k, k, Z, k, Z, k, true, G, k, work, s);
   launch_gram2<float, float>(n, k, k, Z, k, V, ldv, C, k, work, s);
   // G^-1 = R^-1 R^-T  (R: Cholesky factor; R^-1 by the tall solve applied to I)
-  double* mu_d = loss_d + 1;
-  hipLaunchKernelGGL(ridge_kernel, dim3(1), dim3(256), 0, s, k, kRidge, G, mu_d);
-  ISVD_LAUNCH_CHECK();
   launch_cholesky<double>(k, G, k, 0.0, 1e-14, R64, Rc, Dc, flag, s);
   hipLaunchKernelGGL(identity_kernel, dim3(nb(static_cast<int64_t>(k) * lp)), dim3(256), 0, s, k, lp, Rinv);
   ISVD_LAUNCH_CHECK();
@@ -423,7 +395,7 @@ void ws_train_step(isvd_warmstart* ws, int64_t n, const float* F, const float* V
   hipLaunchKernelGGL(spd_inverse_from_rinv_kernel, dim3(nb(static_cast<int64_t>(k) * k)), dim3(256), 0, s, k, lp,
                      Rinv, Ginv);
   ISVD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(loss_small_kernel, dim3(1), dim3(256), 0, s, k, Ginv, C, mu_d, P, PPt, loss_d);
+  hipLaunchKernelGGL(loss_small_kernel, dim3(1), dim3(256), 0, s, k, Ginv, C, P, PPt, loss_d);
   ISVD_LAUNCH_CHECK();
   // dZ = [Z | V] (2/k) [P P^T ; -P^T]
   ws->f64buf.ensure(static_cast<size_t>(2) * k * k * sizeof(float) + static_cast<size_t>(kHid) * kHid * sizeof(float));

@@ -38,7 +38,8 @@ def test_device_gaussian_matches_oracle_philox(gpu_lib):
 # ---------------------------------------------------------------- Gram
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
-@pytest.mark.parametrize("rows,m", [(1, 3), (1000, 42), (70001, 144), (5000, 288)])
+@pytest.mark.parametrize("rows,m", [(1, 3), (1000, 42), (64, 80), (777, 17), (70001, 144), (5000, 288),
+                                    (3001, 600)])
 def test_gram_exact_products_fp64_sums(gpu_lib, dtype, rows, m):
     _print_case("gram", dtype, rows, m)
     y = gaussian_block(rows, m, seed=rows + m)
@@ -51,12 +52,23 @@ def test_gram_exact_products_fp64_sums(gpu_lib, dtype, rows, m):
     assert np.array_equal(g, g.T)
 
 
-def test_gram_rectangular(gpu_lib):
-    _print_case("gram rect")
-    a = rounded(gaussian_block(3001, 20, seed=1), torch.float32)
-    b = rounded(gaussian_block(3001, 70, seed=2), torch.float32)
+@pytest.mark.parametrize("rows,ma,pb", [(3001, 20, 70), (50000, 16, 128), (2000, 130, 5), (4099, 300, 300)])
+def test_gram_rectangular(gpu_lib, rows, ma, pb):
+    _print_case("gram rect", rows, ma, pb)
+    a = rounded(gaussian_block(rows, ma, seed=1), torch.float32)
+    b = rounded(gaussian_block(rows, pb, seed=2), torch.float32)
     c = to_np(gpu_lib.gram(to_dev(a, torch.float32), to_dev(b, torch.float32)))
     assert np.abs(c - a.T @ b).max() <= 1e-13 * np.abs(a.T @ b).max()
+
+
+def test_gram_strided_columns(gpu_lib):
+    # a column window of a wider block: leading dimension larger than the width
+    _print_case("gram strided")
+    wide = rounded(gaussian_block(5003, 160, seed=4), torch.float32)
+    wd = to_dev(wide, torch.float32)
+    g = to_np(gpu_lib.gram(wd[:, 7:151]))
+    want = wide[:, 7:151].T @ wide[:, 7:151]
+    assert np.abs(g - want).max() <= 1e-13 * np.abs(want).max()
 
 
 # ---------------------------------------------------------------- CholeskyQR2

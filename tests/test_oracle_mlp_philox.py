@@ -106,34 +106,6 @@ def test_loss_gradient_matches_central_differences():
     assert np.abs(grad - fd).max() <= 1e-6 * np.abs(fd).max()
 
 
-def test_ridge_loss_gradient_with_mu_held_constant():
-    # with mu frozen at its value at z, the gradient is the exact derivative
-    rng = np.random.default_rng(17)
-    v = _orth(20, 3, 18)
-    z = rng.standard_normal((20, 3))
-    k = 3
-    mu = 1e-1 * np.trace(z.T @ z) / k
-
-    def loss_fixed_mu(zz):
-        g = zz.T @ zz + mu * np.eye(k)
-        pz = zz - v @ (v.T @ zz)
-        return np.trace(np.linalg.inv(g) @ (zz.T @ pz)) / k
-
-    lo, grad = mlp.subspace_loss(z, v, mu_rel=1e-1)
-    assert abs(lo - loss_fixed_mu(z)) < 1e-15
-    h = 1e-6
-    fd = np.zeros_like(z)
-    for i in range(z.shape[0]):
-        for j in range(k):
-            zp, zm = z.copy(), z.copy()
-            zp[i, j] += h
-            zm[i, j] -= h
-            fd[i, j] = (loss_fixed_mu(zp) - loss_fixed_mu(zm)) / (2 * h)
-    assert np.abs(grad - fd).max() <= 1e-6 * np.abs(fd).max()
-    # the ridge only lowers the loss
-    assert lo <= mlp.subspace_loss(z, v)[0] + 1e-15
-
-
 # ---------------------------------------------------------------- network
 
 def test_backward_matches_central_differences():

@@ -111,20 +111,58 @@ __device__ inline void gram_ksteps(const S* As, const S* Bs, int lda_s, int ldb_
   }
 }
 
-// Rows staged per wave and chunk: J rows of CS 64-column steps each (for A
-// and, if B differs, for B).
-template <typename S, int CS, bool SAME>
+// Two adjacent columns of one row in one load (the address is aligned to
+// two elements), converted to the staging type.
+template <typename T, typename S> struct Pair;
+template <typename S> struct Pair<double, S> {
+  __device__ static inline void load(const double* p, S& x, S& y) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    x = static_cast<S>(v.x);
+    y = static_cast<S>(v.y);
+  }
+};
+template <typename S> struct Pair<float, S> {
+  __device__ static inline void load(const float* p, S& x, S& y) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    x = static_cast<S>(v.x);
+    y = static_cast<S>(v.y);
+  }
+};
+template <typename S> struct Pair<bf16, S> {
+  __device__ static inline void load(const bf16* p, S& x, S& y) {
+    const uint32_t v = *reinterpret_cast<const uint32_t*>(p);
+    x = static_cast<S>(bf16_to_float(static_cast<uint16_t>(v & 0xffffu)));
+    y = static_cast<S>(bf16_to_float(static_cast<uint16_t>(v >> 16)));
+  }
+};
+
+// Columns c, c + 1 of a row (c even; zeros at and past `cols`).
+template <int VW, typename T, typename S>
+__device__ inline void gram_load(const T* row, int c, int cols, bool ok, S (&v)[VW]) {
+  if constexpr (VW == 1) {
+    v[0] = (ok && c < cols) ? static_cast<S>(Elem<T>::load(row + c)) : S(0);
+  } else {
+    v[0] = S(0);
+    v[1] = S(0);
+    if (ok && c + 1 < cols) Pair<T, S>::load(row + c, v[0], v[1]);
+    else if (ok && c < cols) v[0] = static_cast<S>(Elem<T>::load(row + c));
+  }
+}
+
+// Rows staged per wave and chunk: J rows of CS steps of 64 VW columns each
+// (for A and, if B differs, for B).
+template <typename S, int CS, int VW, bool SAME>
 constexpr int gram_rows_per_wave() {
-  constexpr int words = CS * static_cast<int>(sizeof(S) / 4) * (SAME ? 1 : 2);
+  constexpr int words = CS * VW * static_cast<int>(sizeof(S) / 4) * (SAME ? 1 : 2);
   return kGramPF / words > 0 ? kGramPF / words : 1;
 }
 
-template <typename TA, typename TB, int CS, bool SAME>
+template <typename TA, typename TB, int CS, int VW, bool SAME>
 __global__ __launch_bounds__(64 * kGramMaxWaves) void gram_partial_kernel(
     int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb, int tm, int tp, int nbi,
     int nbj, int njobs, int64_t rows_per_block, int rb, int ldsa, int ldsb, double* partial, int mp, int pp) {
   using S = typename GramStage<TA, TB>::type;
-  constexpr int J = gram_rows_per_wave<S, CS, SAME>();
+  constexpr int J = gram_rows_per_wave<S, CS, VW, SAME>();
   extern __shared__ __align__(16) unsigned char gram_smem[];
   S* buf0 = reinterpret_cast<S*>(gram_smem);
   const int per_buf = rb * (ldsa + (SAME ? 0 : ldsb));
@@ -162,25 +200,24 @@ __global__ __launch_bounds__(64 * kGramMaxWaves) void gram_partial_kernel(
 
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
-  // wave wv stages chunk rows wv, wv + nw, ...; lane owns columns lane + 64 s
-  S pa[J][CS];
-  S pb[SAME ? 1 : J][SAME ? 1 : CS];
+  // wave wv stages chunk rows wv, wv + nw, ...; lane owns columns
+  // VW lane + 64 VW s .. + VW - 1
+  S pa[J][CS][VW];
+  S pb[SAME ? 1 : J][SAME ? 1 : CS][VW];
   auto fetch = [&](int64_t base) {
-    const TA* a0 = A + (base + wv) * lda + lane;
-    const TB* b0 = B + (base + wv) * ldb + lane;
+    const TA* a0 = A + (base + wv) * lda;
+    const TB* b0 = B + (base + wv) * ldb;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int rl = wv + nw * j;
       const bool ok = rl < rb && base + rl < r1;   // wave-uniform
       const TA* aj = a0 + static_cast<int64_t>(nw * j) * lda;
 #pragma unroll
-      for (int s = 0; s < CS; ++s)
-        pa[j][s] = (ok && lane + 64 * s < m) ? static_cast<S>(Elem<TA>::load(aj + 64 * s)) : S(0);
+      for (int s = 0; s < CS; ++s) gram_load<VW>(aj, VW * lane + 64 * VW * s, m, ok, pa[j][s]);
       if constexpr (!SAME) {
         const TB* bj_ = b0 + static_cast<int64_t>(nw * j) * ldb;
 #pragma unroll
-        for (int s = 0; s < CS; ++s)
-          pb[j][s] = (ok && lane + 64 * s < p) ? static_cast<S>(Elem<TB>::load(bj_ + 64 * s)) : S(0);
+        for (int s = 0; s < CS; ++s) gram_load<VW>(bj_, VW * lane + 64 * VW * s, p, ok, pb[j][s]);
       }
     }
   };
@@ -189,15 +226,19 @@ __global__ __launch_bounds__(64 * kGramMaxWaves) void gram_partial_kernel(
     for (int j = 0; j < J; ++j) {
       const int rl = wv + nw * j;
       if (rl >= rb) continue;
-      S* da = dst + rl * ldsa + lane;
+      S* da = dst + rl * ldsa + VW * lane;
 #pragma unroll
       for (int s = 0; s < CS; ++s)
-        if (lane + 64 * s < mpa) da[64 * s] = pa[j][s];
+        if (VW * lane + 64 * VW * s < mpa)
+#pragma unroll
+          for (int e = 0; e < VW; ++e) da[64 * VW * s + e] = pa[j][s][e];
       if constexpr (!SAME) {
-        S* db = dst + rb * ldsa + rl * ldsb + lane;
+        S* db = dst + rb * ldsa + rl * ldsb + VW * lane;
 #pragma unroll
         for (int s = 0; s < CS; ++s)
-          if (lane + 64 * s < ppa) db[64 * s] = pb[j][s];
+          if (VW * lane + 64 * VW * s < ppa)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) db[64 * VW * s + e] = pb[j][s][e];
       }
     }
   };
@@ -257,7 +298,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int npar
 }
 
 struct GramPlan {
-  int mp, pp, tm, tp, nbi, nbj, njobs, waves, groups, cs, rb, ldsa, ldsb, nparts;
+  int mp, pp, tm, tp, nbi, nbj, njobs, waves, groups, vw, cs, rb, ldsa, ldsb, nparts;
   int64_t rows_per_block;
   size_t lds;
 };
@@ -268,9 +309,10 @@ int64_t gram_rows_per_part(int64_t rows) {
   return round_up(want < 64 ? 64 : want, 64);
 }
 
-constexpr int kGramCS[] = {1, 2, 3, 4, 5, 6, 8, 16, 32};
+constexpr int kGramCS2[] = {1, 2, 3, 4, 5, 6, 8, 16};   // paired-column loads
+constexpr int kGramCS1[] = {1, 2, 4, 8, 16, 32};          // one column per load
 
-GramPlan plan_gram(int64_t rows, int m, int p, bool same, int esize) {
+GramPlan plan_gram(int64_t rows, int m, int p, bool same, int esize, bool paired) {
   GramPlan g;
   g.mp = pad16(m);
   g.pp = pad16(p);
@@ -282,15 +324,24 @@ GramPlan plan_gram(int64_t rows, int m, int p, bool same, int esize) {
   g.groups = static_cast<int>(ceil_div(g.njobs, kGramMaxWaves));
   g.waves = static_cast<int>(ceil_div(g.njobs, g.groups));
   const int mpa = 16 * kGramRB * g.nbi, ppa = 16 * kGramRB * g.nbj;   // staged columns: whole blocks
-  const int need = static_cast<int>(ceil_div(same ? mpa : std::max(mpa, ppa), 64));
+  g.vw = paired ? 2 : 1;
+  const int need = static_cast<int>(ceil_div(same ? mpa : std::max(mpa, ppa), 64 * g.vw));
   g.cs = 0;
-  for (int c : kGramCS)
-    if (c >= need) {
-      g.cs = c;
-      break;
-    }
+  if (paired) {
+    for (int c : kGramCS2)
+      if (c >= need) {
+        g.cs = c;
+        break;
+      }
+  } else {
+    for (int c : kGramCS1)
+      if (c >= need) {
+        g.cs = c;
+        break;
+      }
+  }
   ISVD_CHECK(g.cs > 0, ISVD_E_INVALID, "gram: more than 2048 columns");
-  const int words = g.cs * esize / 4 * (same ? 1 : 2);
+  const int words = g.cs * g.vw * esize / 4 * (same ? 1 : 2);
   const int J = kGramPF / words > 0 ? kGramPF / words : 1;
   if (g.waves * J < 4) g.waves = static_cast<int>(ceil_div(4, J));   // at least one k-step per chunk
   g.ldsa = gram_lds_ld(mpa, esize);
@@ -306,39 +357,55 @@ GramPlan plan_gram(int64_t rows, int m, int p, bool same, int esize) {
   return g;
 }
 
-template <typename TA, typename TB, int CS, bool SAME>
+template <typename TA, typename TB, int CS, int VW, bool SAME>
 void gram_launch(const GramPlan& g, int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
                  double* work, hipStream_t stream) {
-  hipLaunchKernelGGL((gram_partial_kernel<TA, TB, CS, SAME>), dim3(g.nparts, g.groups), dim3(64 * g.waves), g.lds,
-                     stream, rows, m, p, A, lda, B, ldb, g.tm, g.tp, g.nbi, g.nbj, g.njobs, g.rows_per_block, g.rb,
-                     g.ldsa, g.ldsb, work, g.mp, g.pp);
+  hipLaunchKernelGGL((gram_partial_kernel<TA, TB, CS, VW, SAME>), dim3(g.nparts, g.groups), dim3(64 * g.waves),
+                     g.lds, stream, rows, m, p, A, lda, B, ldb, g.tm, g.tp, g.nbi, g.nbj, g.njobs, g.rows_per_block,
+                     g.rb, g.ldsa, g.ldsb, work, g.mp, g.pp);
   ISVD_LAUNCH_CHECK();
 }
 
-template <typename TA, typename TB, int CS>
+template <typename TA, typename TB, int CS, int VW>
 void gram_launch_cs(const GramPlan& g, int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B,
                     int64_t ldb, bool same, double* work, hipStream_t stream) {
   if constexpr (std::is_same<TA, TB>::value) {
-    if (same) return gram_launch<TA, TB, CS, true>(g, rows, m, p, A, lda, B, ldb, work, stream);
+    if (same) return gram_launch<TA, TB, CS, VW, true>(g, rows, m, p, A, lda, B, ldb, work, stream);
   }
-  gram_launch<TA, TB, CS, false>(g, rows, m, p, A, lda, B, ldb, work, stream);
+  gram_launch<TA, TB, CS, VW, false>(g, rows, m, p, A, lda, B, ldb, work, stream);
+}
+
+template <typename T>
+bool gram_pair_ok(const T* ptr, int64_t ld) {
+  return ld % 2 == 0 && (reinterpret_cast<uintptr_t>(ptr) % (2 * sizeof(T))) == 0;
 }
 
 template <typename TA, typename TB>
 void gram_impl(int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
                bool same, double* C, int64_t ldc, double* work, hipStream_t stream) {
   using S = typename GramStage<TA, TB>::type;
-  const GramPlan g = plan_gram(rows, m, p, same, static_cast<int>(sizeof(S)));
-  switch (g.cs) {
-    case 1: gram_launch_cs<TA, TB, 1>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
-    case 2: gram_launch_cs<TA, TB, 2>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
-    case 3: gram_launch_cs<TA, TB, 3>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
-    case 4: gram_launch_cs<TA, TB, 4>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
-    case 5: gram_launch_cs<TA, TB, 5>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
-    case 6: gram_launch_cs<TA, TB, 6>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
-    case 8: gram_launch_cs<TA, TB, 8>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
-    case 16: gram_launch_cs<TA, TB, 16>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
-    default: gram_launch_cs<TA, TB, 32>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+  const bool paired = gram_pair_ok(A, lda) && (same || gram_pair_ok(B, ldb));
+  const GramPlan g = plan_gram(rows, m, p, same, static_cast<int>(sizeof(S)), paired);
+  if (paired) {
+    switch (g.cs) {
+      case 1: gram_launch_cs<TA, TB, 1, 2>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+      case 2: gram_launch_cs<TA, TB, 2, 2>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+      case 3: gram_launch_cs<TA, TB, 3, 2>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+      case 4: gram_launch_cs<TA, TB, 4, 2>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+      case 5: gram_launch_cs<TA, TB, 5, 2>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+      case 6: gram_launch_cs<TA, TB, 6, 2>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+      case 8: gram_launch_cs<TA, TB, 8, 2>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+      default: gram_launch_cs<TA, TB, 16, 2>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+    }
+  } else {
+    switch (g.cs) {
+      case 1: gram_launch_cs<TA, TB, 1, 1>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+      case 2: gram_launch_cs<TA, TB, 2, 1>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+      case 4: gram_launch_cs<TA, TB, 4, 1>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+      case 8: gram_launch_cs<TA, TB, 8, 1>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+      case 16: gram_launch_cs<TA, TB, 16, 1>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+      default: gram_launch_cs<TA, TB, 32, 1>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
+    }
   }
   const int64_t total = static_cast<int64_t>(m) * p;
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(total, 64))), dim3(256),

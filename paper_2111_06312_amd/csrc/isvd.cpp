@@ -9,6 +9,7 @@
 // (Algorithm 1 with iterations = q).  Tolerance mode checks the triplets of
 // iteration t during iteration t+1, whose first product M Qc gives M V for
 // free:  |M v_i - s_i u_i| = column i of [Y | Qr] [U_R; -Z_R S].
+#include <algorithm>
 #include <chrono>
 #include <vector>
 
@@ -26,6 +27,7 @@ struct SvdState {
   DevBuf qc, w, qr, y;
   // small FP64 matrices (padded lp x lp, ld lp)
   DevBuf G, R1, R2, Rc, Rtmp, Rcc, cs_work, sum_c, sum_r, Dc, flag, UR, ZR, sig, jac_work, rhs, left2, right2, gram_work, cn_work, sweeps;
+  DevBuf Rc64, Dc64, X64, Xf;   // explicit-inverse path of the orthonormalisation
   int iterations = 0, applies = 0, bf16_iterations = 0, checks = 0, fallback = 0, ritz_steps = 0;
   double residual = -1.0;
   bool have_ritz = false;
@@ -40,16 +42,50 @@ struct SvdState {
 
 // CholeskyQR2 of Y in place; Rout (optional) receives R2 R1; colsum (optional,
 // l doubles) receives 1^T Q of the stored result.
+// Y <- Y R^-1 for the factor just computed: through the explicit FP64 inverse
+// (MFMA, rows independent) when l allows, else by tiled substitution.
+template <typename T>
+void apply_rinv(SvdState& st, T* Y, int64_t rows, const double* R, bool use_inv, double* colsum,
+                hipStream_t stream) {
+  using C = typename ComputeOf<T>::type;
+  const int l = st.l;
+  if (colsum) st.cs_work.ensure(std::max(trsm_colsum_workspace(l), rinv_apply_workspace(l)) * sizeof(double));
+  if (use_inv) {
+    launch_rinv_prepare<C>(l, R, st.Dc64.as<double>(), st.X64.as<double>(), st.Xf.as<C>(), stream);
+    launch_rinv_apply<T>(rows, l, Y, st.ld, st.Xf.as<C>(), colsum, colsum ? st.cs_work.as<double>() : nullptr,
+                         stream);
+  } else {
+    launch_trsm_tall<T>(rows, l, Y, st.ld, st.Rcc.as<C>(), st.Dc.as<C>(), colsum,
+                        colsum ? st.cs_work.as<double>() : nullptr, stream);
+  }
+}
+
 template <typename T>
 void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* colsum, hipStream_t stream,
                     int npass = 2) {
   using C = typename ComputeOf<T>::type;
   const int l = st.l, lp = st.lp;
+  const bool use_inv = l <= rinv_apply_max_l(static_cast<int>(sizeof(C)));
   st.G.ensure(static_cast<size_t>(l) * l * sizeof(double));
   st.R1.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
   st.R2.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
-  st.Rcc.ensure(static_cast<size_t>(lp) * lp * sizeof(C));
-  st.Dc.ensure(static_cast<size_t>(lp) * 16 * sizeof(C));
+  if (use_inv) {
+    st.Rc64.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
+    st.Dc64.ensure(static_cast<size_t>(lp) * 16 * sizeof(double));
+    st.X64.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
+    st.Xf.ensure(rinv_packed_elems(l) * sizeof(C));
+  } else {
+    st.Rcc.ensure(static_cast<size_t>(lp) * lp * sizeof(C));
+    st.Dc.ensure(static_cast<size_t>(lp) * 16 * sizeof(C));
+  }
+  auto factor = [&](double shift, double rel_tol, double* Rdst) {
+    if (use_inv)
+      launch_cholesky<double>(l, st.G.as<double>(), l, shift, rel_tol, Rdst, st.Rc64.as<double>(),
+                              st.Dc64.as<double>(), st.flag.as<int>(), stream);
+    else
+      launch_cholesky<C>(l, st.G.as<double>(), l, shift, rel_tol, Rdst, st.Rcc.as<C>(), st.Dc.as<C>(),
+                         st.flag.as<int>(), stream);
+  };
   st.flag.ensure(4 * sizeof(int));
   st.gram_work.ensure(gram_workspace_doubles(rows, l, l) * sizeof(double));
   double* Rp[2] = {st.R1.as<double>(), st.R2.as<double>()};
@@ -64,8 +100,7 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* cols
                               hipMemcpyDeviceToDevice, stream));
     }
     launch_gram<T>(rows, l, l, Y, st.ld, Y, st.ld, true, st.G.as<double>(), l, st.gram_work.as<double>(), stream);
-    launch_cholesky<C>(l, st.G.as<double>(), l, 0.0, 1e-14, Rdst, st.Rcc.as<C>(), st.Dc.as<C>(),
-                       st.flag.as<int>(), stream);
+    factor(0.0, 1e-14, Rdst);
     int flag = 0;
     ISVD_HIP(hipMemcpyAsync(&flag, st.flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
     ISVD_HIP(hipStreamSynchronize(stream));
@@ -78,8 +113,7 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* cols
       for (int i = 0; i < l; ++i) tr += g[static_cast<size_t>(i) * l + i];
       const double shift = 11.0 * (static_cast<double>(rows) * l + static_cast<double>(l) * (l + 1)) *
                            1.1102230246251565e-16 * tr;
-      launch_cholesky<C>(l, st.G.as<double>(), l, shift, 0.0, Rdst, st.Rcc.as<C>(), st.Dc.as<C>(),
-                         st.flag.as<int>(), stream);
+      factor(shift, 0.0, Rdst);
       ISVD_HIP(hipMemcpyAsync(&flag, st.flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
       ISVD_HIP(hipStreamSynchronize(stream));
       ISVD_CHECK(flag == 0 && tr > 0.0 && std::isfinite(tr), ISVD_E_NOT_SPD,
@@ -88,9 +122,7 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* cols
       passes = pass + 3 > passes ? pass + 3 : passes;
     }
     const bool last = pass + 1 == passes;
-    if (last && colsum) st.cs_work.ensure(trsm_colsum_workspace(l) * sizeof(double));
-    launch_trsm_tall<T>(rows, l, Y, st.ld, st.Rcc.as<C>(), st.Dc.as<C>(), last ? colsum : nullptr,
-                        last && colsum ? st.cs_work.as<double>() : nullptr, stream);
+    apply_rinv<T>(st, Y, rows, Rdst, use_inv, last ? colsum : nullptr, stream);
   }
   if (Rout) {
     if (passes == 1) launch_convert<double, double>(lp, lp, st.R1.as<double>(), lp, Rout, lp, stream);

@@ -6,8 +6,11 @@ SBM blocks ~ U{5..50}; graph seed 1000 + i) the plain iSVD of
 M = (1/K) sum_{j=1..K} T^j - lambda (11^T - A) gives the target top-k right
 singular vectors (tolerance 1e-3), and isvd_ws_features gives the 16 node
 features.  Training runs epochs of one Adam step per graph through
-isvd_ws_train_step; all arithmetic is in the library's kernels.  Graph
-generation runs in host worker processes while the GPU computes targets.
+isvd_ws_train_step; all arithmetic is in the library's kernels.  The last
+`--val` graphs are held out: after every epoch their mean loss (forward and
+loss only, no update) is measured and the parameters of the best epoch are
+kept.  Graph generation runs in host worker processes while the GPU computes
+targets.
 
 Writes <out>.npy (float32 parameter vector, the isvd_ws_get_params layout)
 and <out>.json (training record).
@@ -51,13 +54,14 @@ def make_graph(i: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--graphs", type=int, default=1000)
-    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--val", type=int, default=50)
     ap.add_argument("--k", type=int, default=128)
     ap.add_argument("--p", type=int, default=16)
     ap.add_argument("--K", type=int, default=10)
     ap.add_argument("--lam", type=float, default=0.1)
     ap.add_argument("--target-tol", type=float, default=1e-3)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--out", default=os.path.join(ROOT, "paper_2111_06312_amd", "weights", "warmstart_k128"))
@@ -85,13 +89,29 @@ def main():
     t_data = time.time() - t0
     ws = lib.WarmStart(args.k, seed=args.seed)
     rng = np.random.default_rng(args.seed)
-    history = []
+    ntrain = len(data) - args.val
+    train, val = data[:ntrain], data[ntrain:]
+
+    def val_loss():
+        out = []
+        for F, V in val:
+            try:
+                out.append(ws.train_step(F, V, lr=0.0)[0])
+            except lib.IsvdError as e:
+                if e.status != lib.ISVD_E_NOT_SPD:
+                    raise
+                out.append(1.0)       # rank-deficient output: no overlap credited
+        return float(np.mean(out)) if out else float("nan")
+
+    best = (val_loss(), -1, ws.get_params())
+    print(f"[train] initial validation loss {best[0]:.4f}", flush=True)
+    history, val_history = [], []
     for ep in range(args.epochs):
-        order = rng.permutation(len(data))
+        order = rng.permutation(len(train))
         losses = []
         skipped = 0
         for j in order:
-            F, V = data[j]
+            F, V = train[j]
             try:
                 loss, _ = ws.train_step(F, V, lr=args.lr)
             except lib.IsvdError as e:
@@ -101,16 +121,22 @@ def main():
                 continue
             losses.append(loss)
         history.append(float(np.mean(losses)) if losses else float("nan"))
+        val_history.append(val_loss())
+        if val_history[-1] < best[0]:
+            best = (val_history[-1], ep, ws.get_params())
         if skipped:
             print(f"[train] epoch {ep}: {skipped} steps skipped (rank-deficient output)", flush=True)
-        print(f"[train] epoch {ep}: mean loss {history[-1]:.4f} ({time.time() - t0:.0f} s)", flush=True)
+        print(f"[train] epoch {ep}: mean loss {history[-1]:.4f}, validation {val_history[-1]:.4f} "
+              f"({time.time() - t0:.0f} s)", flush=True)
     torch.cuda.synchronize()
-    os.makedirs(os.path.dirname(args.out), exist_ok=True)
-    np.save(args.out + ".npy", ws.get_params())
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    np.save(args.out + ".npy", best[2])
     with open(args.out + ".json", "w") as fh:
         json.dump({"k": args.k, "p": args.p, "K": args.K, "lambda": args.lam, "graphs": args.graphs,
-                   "epochs": args.epochs, "lr": args.lr, "target_tol": args.target_tol, "seed": args.seed,
-                   "loss_per_epoch": history, "seconds_targets": round(t_data, 1),
+                   "validation_graphs": args.val, "epochs": args.epochs, "lr": args.lr,
+                   "target_tol": args.target_tol, "seed": args.seed, "best_epoch": best[1],
+                   "best_validation_loss": best[0], "loss_per_epoch": history,
+                   "validation_loss_per_epoch": val_history, "seconds_targets": round(t_data, 1),
                    "seconds_total": round(time.time() - t0, 1)}, fh, indent=1)
     print(f"[train] wrote {args.out}.npy", flush=True)
 

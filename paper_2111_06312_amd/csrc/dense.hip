@@ -850,10 +850,10 @@ constexpr int kApplyParts = 1024;
 
 // Y <- Y X, X upper triangular (packed by rinv_pack_kernel), in place.  Each
 // wave owns 16 rows at a time: it reads all of them into registers (as MFMA A
-// operands), then forms the output column tiles K = 0..TT-1 independently,
-// tile K as sum over J <= K of Y_J X_JK, and stores each tile as soon as it is
-// complete (its inputs, the wave's own rows, are already in registers).  With
-// colpart, each block writes the FP64 column sums of the values it stored.
+// operands), then forms the output column tiles K = 0..TT-1, tile K as the sum
+// over J <= K of Y_J X_JK, and stores each tile as soon as it is complete (its
+// inputs, the wave's own rows, are already in registers).  With colpart, each
+// block writes the FP64 column sums of the values it stored.
 template <typename T, typename C, int MT>
 __global__ __launch_bounds__(256) void rinv_apply_kernel(int64_t rows, int l, T* Y, int64_t ld, int vec,
                                                          const C* Xf, double* colpart) {
@@ -878,41 +878,39 @@ __global__ __launch_bounds__(256) void rinv_apply_kernel(int64_t rows, int l, T*
     }
 #pragma unroll 1
     for (int K = 0; K < TT; ++K) {
-      {
-        V acc = V{0, 0, 0, 0};
-        const C* xs = Xf + static_cast<int64_t>(K * (K + 1) / 2) * 256 + 4 * lane;
+      V acc = V{0, 0, 0, 0};
+      const C* xs = Xf + static_cast<int64_t>(K * (K + 1) / 2) * 256 + 4 * lane;
 #pragma unroll
-        for (int J = 0; J < MT; ++J) {
-          if (J > K) continue;
-          C b[4];
-          if constexpr (std::is_same<C, float>::value) {
-            const float4 q = *reinterpret_cast<const float4*>(xs + 256 * J);
-            b[0] = q.x; b[1] = q.y; b[2] = q.z; b[3] = q.w;
-          } else {
-            const double2 q0 = *reinterpret_cast<const double2*>(xs + 256 * J);
-            const double2 q1 = *reinterpret_cast<const double2*>(xs + 256 * J + 2);
-            b[0] = q0.x; b[1] = q0.y; b[2] = q1.x; b[3] = q1.y;
-          }
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) acc = mfma4(ya[J][kk], b[kk], acc);
+      for (int J = 0; J < MT; ++J) {
+        if (J > K) continue;
+        C b[4];
+        if constexpr (std::is_same<C, float>::value) {
+          const float4 q = *reinterpret_cast<const float4*>(xs + 256 * J);
+          b[0] = q.x; b[1] = q.y; b[2] = q.z; b[3] = q.w;
+        } else {
+          const double2 q0 = *reinterpret_cast<const double2*>(xs + 256 * J);
+          const double2 q1 = *reinterpret_cast<const double2*>(xs + 256 * J + 2);
+          b[0] = q0.x; b[1] = q0.y; b[2] = q1.x; b[3] = q1.y;
         }
-        const int col = 16 * K + li;
-        double s = 0.0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t row = row0 + drow<C>(lk, r);
-          if (row < rows && col < l) {
-            Elem<T>::store(Y + row * ld + col, acc[r]);
-            s += static_cast<double>(stored_as<T, C>(acc[r]));
-          }
-        }
-        if (colpart) {
-          s += __shfl_xor(s, 16, 64);
-          s += __shfl_xor(s, 32, 64);
+        for (int kk = 0; kk < 4; ++kk) acc = mfma4(ya[J][kk], b[kk], acc);
+      }
+      const int col = 16 * K + li;
+      double sum = 0.0;
 #pragma unroll
-          for (int c = 0; c < NC; ++c)
-            if (4 * c + lk == K) cs[c] += s;
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + drow<C>(lk, r);
+        if (row < rows && col < l) {
+          Elem<T>::store(Y + row * ld + col, acc[r]);
+          sum += static_cast<double>(stored_as<T, C>(acc[r]));
         }
+      }
+      if (colpart) {
+        sum += __shfl_xor(sum, 16, 64);
+        sum += __shfl_xor(sum, 32, 64);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (4 * c + lk == K) cs[c] += sum;
       }
     }
   }

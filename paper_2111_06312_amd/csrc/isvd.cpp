@@ -11,6 +11,7 @@
 // free:  |M v_i - s_i u_i| = column i of [Y | Qr] [U_R; -Z_R S].
 #include <algorithm>
 #include <chrono>
+#include <type_traits>
 #include <vector>
 
 #include "operator.h"
@@ -65,7 +66,10 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* cols
                     int npass = 2) {
   using C = typename ComputeOf<T>::type;
   const int l = st.l, lp = st.lp;
-  const bool use_inv = l <= rinv_apply_max_l(static_cast<int>(sizeof(C)));
+  // The explicit inverse is not backward stable (its error grows with
+  // kappa(R) u of the compute type); BF16 blocks, whose own rounding is of
+  // that size, keep the substitution so their phase is not cut short.
+  const bool use_inv = !std::is_same<T, bf16>::value && l <= rinv_apply_max_l(static_cast<int>(sizeof(C)));
   st.G.ensure(static_cast<size_t>(l) * l * sizeof(double));
   st.R1.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
   st.R2.ensure(static_cast<size_t>(lp) * lp * sizeof(double));

@@ -86,8 +86,10 @@ void launch_upper_mult(int l, const double* A, const double* B, double* C, int64
 
 size_t jacobi_workspace_doubles(int n);
 // A (n x n, FP64 row-major lda) = U diag(s) V^T; U, V n x n row-major (ld n), s descending.
+// V0 (optional, n x n orthogonal, ld n, may alias V): starting rotation for the
+// block-parallel path (64 < n <= 512), e.g. the previous V of a slowly changing A.
 void launch_jacobi_svd(int n, const double* A, int64_t lda, double* U, double* s, double* V,
-                       double* work, int* sweeps_out, hipStream_t stream);
+                       double* work, int* sweeps_out, hipStream_t stream, const double* V0 = nullptr);
 
 // ---------------------------------------------------------------- misc
 

@@ -1149,14 +1149,28 @@ __global__ __launch_bounds__(kBJThreads) void bjacobi_round_kernel(int n, int nb
   if (threadIdx.x == 0 && any_rot) flags[1 + sweep] = 1;
 }
 
-__global__ void bjacobi_init_kernel(int n, int np, const double* A, int64_t lda, double* Wt, double* Jt, int* flags,
-                                    int nflags) {
+// Row p of Wt = column p of A V0, row p of Jt = column p of V0 (V0 = I when
+// absent): the sweeps then rotate A V0, and the accumulated rotation starts at
+// V0, so a V0 close to A's right singular vectors saves sweeps and any
+// orthogonal V0 gives the same decomposition.
+__global__ void bjacobi_init_kernel(int n, int np, const double* A, int64_t lda, const double* V0, double* Wt,
+                                    double* Jt, int* flags, int nflags) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx < nflags) flags[idx] = 0;
   if (idx >= static_cast<int64_t>(np) * n) return;
   const int p = static_cast<int>(idx / n), i = static_cast<int>(idx % n);
-  Wt[idx] = p < n ? A[static_cast<int64_t>(i) * lda + p] : 0.0;
-  Jt[idx] = (p == i) ? 1.0 : 0.0;
+  if (V0 == nullptr) {
+    Wt[idx] = p < n ? A[static_cast<int64_t>(i) * lda + p] : 0.0;
+    Jt[idx] = (p == i) ? 1.0 : 0.0;
+  } else if (p < n) {
+    double w = 0.0;
+    for (int q = 0; q < n; ++q) w += A[static_cast<int64_t>(i) * lda + q] * V0[static_cast<int64_t>(q) * n + p];
+    Wt[idx] = w;
+    Jt[idx] = V0[static_cast<int64_t>(i) * n + p];
+  } else {
+    Wt[idx] = 0.0;
+    Jt[idx] = 0.0;
+  }
 }
 
 __global__ void bjacobi_check_kernel(int sweep, int* flags) {
@@ -1465,7 +1479,7 @@ size_t jacobi_workspace_doubles(int n) {
 }
 
 void launch_jacobi_svd(int n, const double* A, int64_t lda, double* U, double* s, double* V, double* work,
-                       int* sweeps_out, hipStream_t stream) {
+                       int* sweeps_out, hipStream_t stream, const double* V0) {
   ISVD_CHECK(n >= 1 && n <= kJacobiMaxN, ISVD_E_INVALID, "small svd: n out of range");
   if (n <= 64 || n > 512) {
     // one workgroup, pairs held in registers
@@ -1493,7 +1507,7 @@ void launch_jacobi_svd(int n, const double* A, int64_t lda, double* U, double* s
   const int nflags = 1 + 64 + 2;
   const int64_t total = static_cast<int64_t>(np) * n;
   hipLaunchKernelGGL(bjacobi_init_kernel, dim3(static_cast<unsigned>(ceil_div(total, 256))), dim3(256), 0, stream, n, np,
-                     A, lda, Wt, Jt, flags, nflags);
+                     A, lda, V0, Wt, Jt, flags, nflags);
   ISVD_LAUNCH_CHECK();
   const size_t lds = static_cast<size_t>(4) * B * n * sizeof(double);
   constexpr int kMaxSweeps = 40;

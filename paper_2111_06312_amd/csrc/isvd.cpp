@@ -32,11 +32,13 @@ struct SvdState {
   int iterations = 0, applies = 0, bf16_iterations = 0, checks = 0, fallback = 0, ritz_steps = 0;
   double residual = -1.0;
   bool have_ritz = false;
+  bool zr_valid = false;   // ZR holds the right rotation of an earlier Ritz step of this call
   int ritz_iter = -1;
   void reset_counters() {
     iterations = applies = bf16_iterations = checks = fallback = ritz_steps = 0;
     residual = -1.0;
     have_ritz = false;
+    zr_valid = false;
     ritz_iter = -1;
   }
 };
@@ -141,9 +143,13 @@ void ritz(SvdState& st, hipStream_t stream) {
   st.sig.ensure(static_cast<size_t>(l) * sizeof(double));
   st.jac_work.ensure(jacobi_workspace_doubles(l) * sizeof(double));
   st.sweeps.ensure(sizeof(int));
+  // the bases change slowly between Rayleigh-Ritz steps, so the previous right
+  // rotation Z_R nearly diagonalises the new R's columns: start the sweeps there
   launch_jacobi_svd(l, st.Rc.as<double>(), lp, st.UR.as<double>(), st.sig.as<double>(), st.ZR.as<double>(),
-                    st.jac_work.as<double>(), st.sweeps.as<int>(), stream);
+                    st.jac_work.as<double>(), st.sweeps.as<int>(), stream,
+                    st.zr_valid ? st.ZR.as<double>() : nullptr);
   st.have_ritz = true;
+  st.zr_valid = true;
   st.ritz_steps++;
 }
 

@@ -138,15 +138,18 @@ isvd_status isvd_matmul_block(isvd_operator* op, int transpose, const void* Y, i
  *                rho = max_i sqrt(|M v_i - s_i u_i|^2 + |M^T u_i - s_i v_i|^2) / s_i
  *              is <= tol, or max_iter iterations.
  *  check_every : tolerance mode checks rho every this many iterations; 0 =
- *              adaptive (checks placed where the observed geometric decay of rho
- *              predicts the tolerance, at most 32 iterations apart).
+ *              adaptive (first check after iteration 2, then 4 iterations later,
+ *              then where the observed geometric decay of rho predicts the
+ *              tolerance, at most 48 iterations apart).
  *  seed      : Philox seed for a device-drawn Gaussian start block when omega is NULL.
  *  omega     : optional device c x l start block (operator precision, leading
  *              dimension ld_omega), used verbatim.
  *  fp32_switch_tol : BF16 operators only; when > 0 the iteration continues
- *              in FP32 once rho <= fp32_switch_tol, or once a check improves rho
- *              by less than 10% (the BF16 rounding floor; BF16 alone cannot reach
- *              small residuals).  U and V are float for BF16 operators. */
+ *              in FP32 once rho <= fp32_switch_tol, or once rho has fallen by
+ *              less than 2% per iteration since the previous check (the BF16
+ *              rounding floor; BF16 alone cannot reach small residuals), or
+ *              after bf16_max_iter iterations when that is > 0 (which replaces
+ *              the 2% rule).  U and V are float for BF16 operators. */
 typedef struct {
   int k;
   int p;

@@ -63,20 +63,20 @@ void launch_trsm_tall(int64_t rows, int l, T* Y, int64_t ld, const typename Comp
                       hipStream_t stream);
 inline size_t trsm_colsum_workspace(int l) { return static_cast<size_t>(1024) * l; }
 
-// Y <- Y R^-1 through the explicit inverse (used when l is at most
-// rinv_apply_max_l(sizeof compute type)): launch_rinv_prepare forms
-// X = R^-1 in FP64 (X64: lp x lp scratch) from launch_cholesky<double>'s R64
-// and Dinv, and packs it for the MFMA operands (Xf: rinv_packed_elems(l)
-// values); launch_rinv_apply multiplies in place.  colsum as for
-// launch_trsm_tall (work: rinv_apply_workspace doubles).
-int rinv_apply_max_l(int esize);
-size_t rinv_packed_elems(int l);
-inline size_t rinv_apply_workspace(int l) { return static_cast<size_t>(1024) * l; }
+// Y <- Y R^-1 with the block's rows in registers (used when l is at most
+// trsm_rows_max_l(sizeof compute type)): launch_trsm_rows_pack packs
+// launch_cholesky<double>'s R64 and the inverses of its diagonal tiles for the
+// MFMA operands (Rf: trsm_rows_packed_elems(l) values of the compute type);
+// launch_trsm_rows solves in place.  colsum as for launch_trsm_tall (work:
+// trsm_rows_workspace doubles).
+int trsm_rows_max_l(int esize);
+size_t trsm_rows_packed_elems(int l);
+inline size_t trsm_rows_workspace(int l) { return static_cast<size_t>(1024) * l; }
 template <typename C>
-void launch_rinv_prepare(int l, const double* R64, const double* Dinv64, double* X64, C* Xf, hipStream_t stream);
+void launch_trsm_rows_pack(int l, const double* R64, const double* Dinv64, C* Rf, hipStream_t stream);
 template <typename T>
-void launch_rinv_apply(int64_t rows, int l, T* Y, int64_t ld, const typename ComputeOf<T>::type* Xf, double* colsum,
-                       double* work, hipStream_t stream);
+void launch_trsm_rows(int64_t rows, int l, T* Y, int64_t ld, const typename ComputeOf<T>::type* Rf, double* colsum,
+                      double* work, hipStream_t stream);
 
 // C = A * B for upper-triangular l x l FP64 matrices (padded lp, ld lp).
 void launch_upper_mult(int l, const double* A, const double* B, double* C, int64_t ld,

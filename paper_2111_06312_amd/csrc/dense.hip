@@ -797,16 +797,24 @@ __global__ void upper_mult_kernel(int lp, const double* A, const double* B, doub
   Cm[static_cast<int64_t>(i) * ld + j] = (i <= j) ? s : 0.0;
 }
 
-// ============================================================ tall Y <- Y R^-1 by an explicit inverse
+// ============================================================ tall Y <- Y R^-1, rows in registers
 
-// The inverse X = R^-1 (upper triangular, lp x lp FP64) packed for the MFMA
-// B operand: tiles (J, K), J <= K, column tile by column tile (tile index
-// K (K + 1) / 2 + J), 256 entries each; entry (16 lk + li) 4 + kk holds
-// X[16 J + 4 lk + kk][16 K + li].  Lane (li, lk) then reads four consecutive
-// values for the k-steps kk = 0..3, and the A operand of step kk is column
-// 16 J + 4 lk + kk of row li of the Y tile: four consecutive values of one row.
+// Transposed form: the column tiles of Q = Y R^-1 satisfy
+//   Q_K^T = D_K^T (Y_K^T - sum_{J<K} R_JK^T Q_J^T),   D_K = (R_KK)^-1,
+// an MFMA problem in which every Q_J^T is a B operand.  The MFMA accumulator
+// layout (lane (li, lk), value r holds row drow(lk, r), column li) is the B
+// operand layout for k-step kk = r under the k-index order k = drow(lk, kk),
+// so each output tile serves as an operand of the later tiles straight from
+// registers, and lane (li, lk) reads and writes elements drow(lk, 0..3) of
+// row li of its 16-row tile (four consecutive FP32 values).
+//
+// The A operands R_JK^T and D_K^T are packed once per factor: tiles (J, K),
+// J <= K, column tile by column tile (tile index K (K + 1) / 2 + J), 256
+// entries each, entry (16 lk + li) 4 + kk holding R[16 J + drow(lk, kk)][16 K + li]
+// (J < K) or D_K[drow(lk, kk)][li] (J = K): one 16-byte read per lane gives the
+// four k-steps.
 template <typename C>
-__global__ void rinv_pack_kernel(int lp, const double* X, C* Xf) {
+__global__ void rfrag_pack_kernel(int lp, const double* R, const double* Dinv, C* Rf) {
   const int TT = lp / 16;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= static_cast<int64_t>(TT) * (TT + 1) / 2 * 256) return;
@@ -815,125 +823,157 @@ __global__ void rinv_pack_kernel(int lp, const double* X, C* Xf) {
   while ((K + 1) * (K + 2) / 2 <= t) ++K;
   const int J = t - K * (K + 1) / 2;
   const int kk = e & 3, li = (e >> 2) & 15, lk = e >> 6;
-  Xf[idx] = static_cast<C>(X[static_cast<int64_t>(16 * J + 4 * lk + kk) * lp + 16 * K + li]);
+  const int a = drow<C>(lk, kk);
+  const double v = (J < K) ? R[static_cast<int64_t>(16 * J + a) * lp + 16 * K + li] : Dinv[K * 256 + a * 16 + li];
+  Rf[idx] = static_cast<C>(v);
 }
 
 // The value an element takes once stored in T.
 template <typename T, typename C> __device__ inline C stored_as(C v) { return v; }
 template <> __device__ inline float stored_as<bf16, float>(float v) { return bf16_to_float(float_to_bf16(v)); }
 
-// Four consecutive elements c0..c0+3 of one row (zeros past `cols` or when !ok).
+// Elements drow(lk, 0..3) of tile K of one row (zeros past `cols` or when !ok).
 template <typename T, typename C>
-__device__ inline void load_row4(const T* rowp, int c0, int cols, bool ok, bool vec, C (&v)[4]) {
-  if (ok && vec && c0 + 3 < cols) {
-    if constexpr (std::is_same<T, float>::value) {
-      const float4 q = *reinterpret_cast<const float4*>(rowp + c0);
-      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-    } else if constexpr (std::is_same<T, double>::value) {
-      const double2 a = *reinterpret_cast<const double2*>(rowp + c0);
-      const double2 b = *reinterpret_cast<const double2*>(rowp + c0 + 2);
-      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-    } else {
-      const uint2 q = *reinterpret_cast<const uint2*>(rowp + c0);
-      v[0] = bf16_to_float(static_cast<uint16_t>(q.x & 0xffffu));
-      v[1] = bf16_to_float(static_cast<uint16_t>(q.x >> 16));
-      v[2] = bf16_to_float(static_cast<uint16_t>(q.y & 0xffffu));
-      v[3] = bf16_to_float(static_cast<uint16_t>(q.y >> 16));
+__device__ inline void load_tile_row(const T* rowp, int K, int lk, int cols, bool ok, bool vec, C (&v)[4]) {
+  if constexpr (!std::is_same<C, double>::value) {
+    const int c0 = 16 * K + 4 * lk;
+    if (ok && vec && c0 + 3 < cols) {
+      if constexpr (std::is_same<T, float>::value) {
+        const float4 q = *reinterpret_cast<const float4*>(rowp + c0);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+      } else {
+        const uint2 q = *reinterpret_cast<const uint2*>(rowp + c0);
+        v[0] = bf16_to_float(static_cast<uint16_t>(q.x & 0xffffu));
+        v[1] = bf16_to_float(static_cast<uint16_t>(q.x >> 16));
+        v[2] = bf16_to_float(static_cast<uint16_t>(q.y & 0xffffu));
+        v[3] = bf16_to_float(static_cast<uint16_t>(q.y >> 16));
+      }
+      return;
     }
-  } else {
+  }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = (ok && c0 + e < cols) ? ld_as<C>(rowp + c0 + e) : C(0);
+  for (int r = 0; r < 4; ++r) {
+    const int c = 16 * K + drow<C>(lk, r);
+    v[r] = (ok && c < cols) ? ld_as<C>(rowp + c) : C(0);
   }
 }
 
-constexpr int kApplyParts = 1024;
+template <typename T, typename C>
+__device__ inline void store_tile_row(T* rowp, int K, int lk, int cols, bool ok, bool vec, const C (&v)[4]) {
+  if (!ok) return;
+  if constexpr (!std::is_same<C, double>::value) {
+    const int c0 = 16 * K + 4 * lk;
+    if (vec && c0 + 3 < cols) {
+      if constexpr (std::is_same<T, float>::value) {
+        *reinterpret_cast<float4*>(rowp + c0) = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+        const uint32_t a = static_cast<uint32_t>(float_to_bf16(v[0])) | (static_cast<uint32_t>(float_to_bf16(v[1])) << 16);
+        const uint32_t b = static_cast<uint32_t>(float_to_bf16(v[2])) | (static_cast<uint32_t>(float_to_bf16(v[3])) << 16);
+        *reinterpret_cast<uint2*>(rowp + c0) = make_uint2(a, b);
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int c = 16 * K + drow<C>(lk, r);
+    if (c < cols) Elem<T>::store(rowp + c, v[r]);
+  }
+}
 
-// Y <- Y X, X upper triangular (packed by rinv_pack_kernel), in place.  Each
-// wave owns 16 rows at a time: it reads all of them into registers (as MFMA A
-// operands), then forms the output column tiles K = 0..TT-1, tile K as the sum
-// over J <= K of Y_J X_JK, and stores each tile as soon as it is complete (its
-// inputs, the wave's own rows, are already in registers).  With colpart, each
-// block writes the FP64 column sums of the values it stored.
+template <typename C>
+__device__ inline void load_frag4(const C* p, C (&b)[4]) {
+  if constexpr (std::is_same<C, float>::value) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    b[0] = q.x; b[1] = q.y; b[2] = q.z; b[3] = q.w;
+  } else {
+    const double2 q0 = *reinterpret_cast<const double2*>(p);
+    const double2 q1 = *reinterpret_cast<const double2*>(p + 2);
+    b[0] = q0.x; b[1] = q0.y; b[2] = q1.x; b[3] = q1.y;
+  }
+}
+
+constexpr int kRowsTrsmParts = 1024;
+
+// Each wave owns 16 rows at a time and walks the column tiles K in order; the
+// finished tiles Q_J^T stay in its registers as B operands.  The sum over J is
+// split over four accumulators (independent MFMA chains).  Tile K of Y is read
+// just before it is overwritten by Q_K.  With colpart, each block writes the
+// FP64 column sums of the values it stored (per wave in LDS, then in a fixed
+// order over the waves).
 template <typename T, typename C, int MT>
-__global__ __launch_bounds__(256) void rinv_apply_kernel(int64_t rows, int l, T* Y, int64_t ld, int vec,
-                                                         const C* Xf, double* colpart) {
+__global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* Y, int64_t ld, int vec,
+                                                        const C* Rf, double* colpart) {
   using V = typename Acc4<C>::type;
-  constexpr int NC = (MT + 3) / 4;
-  __shared__ double red[4][16 * MT];
+  __shared__ double csw[4][16 * MT];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int TT = (l + 15) / 16;
-  double cs[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) cs[c] = 0.0;
+  if (colpart) {
+    for (int c = lane; c < 16 * MT; c += 64) csw[wave][c] = 0.0;
+  }
   const int64_t ntiles = (rows + 15) / 16;
   for (int64_t rt = static_cast<int64_t>(blockIdx.x) * 4 + wave; rt < ntiles; rt += static_cast<int64_t>(gridDim.x) * 4) {
     const int64_t row0 = rt * 16;
     const bool rok = row0 + li < rows;
-    const T* rowp = Y + (row0 + li) * ld;
-    C ya[MT][4];
-#pragma unroll
-    for (int J = 0; J < MT; ++J) {
-      if (J < TT) load_row4<T, C>(rowp, 16 * J + 4 * lk, l, rok, vec != 0, ya[J]);
-    }
+    T* rowp = Y + (row0 + li) * ld;
+    C q[MT][4];
 #pragma unroll 1
     for (int K = 0; K < TT; ++K) {
-      V acc = V{0, 0, 0, 0};
-      const C* xs = Xf + static_cast<int64_t>(K * (K + 1) / 2) * 256 + 4 * lane;
+      C y[4];
+      load_tile_row<T, C>(rowp, K, lk, l, rok, vec != 0, y);
+      V acc[4];
+      acc[0] = V{y[0], y[1], y[2], y[3]};
+      acc[1] = acc[2] = acc[3] = V{0, 0, 0, 0};
+      const C* rk = Rf + static_cast<int64_t>(K * (K + 1) / 2) * 256 + 4 * lane;
 #pragma unroll
       for (int J = 0; J < MT; ++J) {
-        if (J > K) continue;
-        C b[4];
-        if constexpr (std::is_same<C, float>::value) {
-          const float4 q = *reinterpret_cast<const float4*>(xs + 256 * J);
-          b[0] = q.x; b[1] = q.y; b[2] = q.z; b[3] = q.w;
-        } else {
-          const double2 q0 = *reinterpret_cast<const double2*>(xs + 256 * J);
-          const double2 q1 = *reinterpret_cast<const double2*>(xs + 256 * J + 2);
-          b[0] = q0.x; b[1] = q0.y; b[2] = q1.x; b[3] = q1.y;
-        }
+        if (J >= K) continue;
+        C a[4];
+        load_frag4<C>(rk + 256 * J, a);
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) acc = mfma4(ya[J][kk], b[kk], acc);
+        for (int kk = 0; kk < 4; ++kk) acc[J & 3] = mfma4(-a[kk], q[J][kk], acc[J & 3]);
       }
-      const int col = 16 * K + li;
-      double sum = 0.0;
+      const V sacc = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+      C d[4];
+      load_frag4<C>(rk + 256 * K, d);
+      V out = V{0, 0, 0, 0};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = row0 + drow<C>(lk, r);
-        if (row < rows && col < l) {
-          Elem<T>::store(Y + row * ld + col, acc[r]);
-          sum += static_cast<double>(stored_as<T, C>(acc[r]));
+      for (int kk = 0; kk < 4; ++kk) out = mfma4(d[kk], sacc[kk], out);
+      C o[4] = {out[0], out[1], out[2], out[3]};
+#pragma unroll
+      for (int J = 0; J < MT; ++J)
+        if (J == K) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) q[J][r] = o[r];
         }
-      }
+      store_tile_row<T, C>(rowp, K, lk, l, rok, vec != 0, o);
       if (colpart) {
-        sum += __shfl_xor(sum, 16, 64);
-        sum += __shfl_xor(sum, 32, 64);
+        double cs[4];
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
-          if (4 * c + lk == K) cs[c] += sum;
+        for (int r = 0; r < 4; ++r) {
+          const int c = 16 * K + drow<C>(lk, r);
+          cs[r] = (rok && c < l) ? static_cast<double>(stored_as<T, C>(o[r])) : 0.0;
+#pragma unroll
+          for (int m = 1; m < 16; m <<= 1) cs[r] += __shfl_xor(cs[r], m, 64);
+        }
+        if (li == 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) csw[wave][16 * K + drow<C>(lk, r)] += cs[r];
+        }
       }
     }
   }
   if (colpart) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int K = 4 * c + lk;
-      if (K < MT) red[wave][16 * K + li] = cs[c];
-    }
     __syncthreads();
     for (int col = threadIdx.x; col < l; col += blockDim.x)
-      colpart[static_cast<int64_t>(blockIdx.x) * l + col] = (red[0][col] + red[1][col]) + (red[2][col] + red[3][col]);
+      colpart[static_cast<int64_t>(blockIdx.x) * l + col] = (csw[0][col] + csw[1][col]) + (csw[2][col] + csw[3][col]);
   }
 }
 
 __global__ void zero_doubles_kernel(int64_t n, double* x) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx < n) x[idx] = 0.0;
-}
-
-__global__ void identity_pad_kernel(int lp, double* X) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx < static_cast<int64_t>(lp) * lp) X[idx] = (idx / lp == idx % lp) ? 1.0 : 0.0;
 }
 
 // ============================================================ one-sided Jacobi SVD
@@ -1393,44 +1433,38 @@ template void launch_trsm_tall<double>(int64_t, int, double*, int64_t, const dou
 template void launch_trsm_tall<float>(int64_t, int, float*, int64_t, const float*, const float*, double*, double*, hipStream_t);
 template void launch_trsm_tall<bf16>(int64_t, int, bf16*, int64_t, const float*, const float*, double*, double*, hipStream_t);
 
-int rinv_apply_max_l(int esize) { return esize == 8 ? 128 : 320; }
+int trsm_rows_max_l(int esize) { return esize == 8 ? 128 : 320; }
 
-size_t rinv_packed_elems(int l) {
+size_t trsm_rows_packed_elems(int l) {
   const int TT = pad16(l) / 16;
   return static_cast<size_t>(TT) * (TT + 1) / 2 * 256;
 }
 
 template <typename C>
-void launch_rinv_prepare(int l, const double* R64, const double* Dinv64, double* X64, C* Xf, hipStream_t stream) {
+void launch_trsm_rows_pack(int l, const double* R64, const double* Dinv64, C* Rf, hipStream_t stream) {
   const int lp = pad16(l);
-  const int64_t n2 = static_cast<int64_t>(lp) * lp;
-  hipLaunchKernelGGL(identity_pad_kernel, dim3(static_cast<unsigned>(ceil_div(n2, 256))), dim3(256), 0, stream, lp,
-                     X64);
-  ISVD_LAUNCH_CHECK();
-  // X = I R^-1 by the tall substitution on the l rows of the identity
-  launch_trsm_tall<double>(l, l, X64, lp, R64, Dinv64, nullptr, nullptr, stream);
-  const int64_t total = static_cast<int64_t>(rinv_packed_elems(l));
-  hipLaunchKernelGGL((rinv_pack_kernel<C>), dim3(static_cast<unsigned>(ceil_div(total, 256))), dim3(256), 0, stream,
-                     lp, X64, Xf);
+  const int64_t total = static_cast<int64_t>(trsm_rows_packed_elems(l));
+  hipLaunchKernelGGL((rfrag_pack_kernel<C>), dim3(static_cast<unsigned>(ceil_div(total, 256))), dim3(256), 0, stream,
+                     lp, R64, Dinv64, Rf);
   ISVD_LAUNCH_CHECK();
 }
-template void launch_rinv_prepare<double>(int, const double*, const double*, double*, double*, hipStream_t);
-template void launch_rinv_prepare<float>(int, const double*, const double*, double*, float*, hipStream_t);
+template void launch_trsm_rows_pack<double>(int, const double*, const double*, double*, hipStream_t);
+template void launch_trsm_rows_pack<float>(int, const double*, const double*, float*, hipStream_t);
 
 template <typename T, typename C, int MT>
-void rinv_apply_launch(int64_t rows, int l, T* Y, int64_t ld, int vec, const C* Xf, double* colpart, int64_t grid,
-                       hipStream_t stream) {
-  hipLaunchKernelGGL((rinv_apply_kernel<T, C, MT>), dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, rows, l,
-                     Y, ld, vec, Xf, colpart);
+void trsm_rows_launch(int64_t rows, int l, T* Y, int64_t ld, int vec, const C* Rf, double* colpart, int64_t grid,
+                      hipStream_t stream) {
+  hipLaunchKernelGGL((trsm_rows_kernel<T, C, MT>), dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, rows, l,
+                     Y, ld, vec, Rf, colpart);
   ISVD_LAUNCH_CHECK();
 }
 
 template <typename T>
-void launch_rinv_apply(int64_t rows, int l, T* Y, int64_t ld, const typename ComputeOf<T>::type* Xf, double* colsum,
-                       double* work, hipStream_t stream) {
+void launch_trsm_rows(int64_t rows, int l, T* Y, int64_t ld, const typename ComputeOf<T>::type* Rf, double* colsum,
+                      double* work, hipStream_t stream) {
   using C = typename ComputeOf<T>::type;
-  ISVD_CHECK(l >= 1 && l <= rinv_apply_max_l(static_cast<int>(sizeof(C))), ISVD_E_INVALID,
-             "explicit-inverse apply: l out of range");
+  ISVD_CHECK(l >= 1 && l <= trsm_rows_max_l(static_cast<int>(sizeof(C))), ISVD_E_INVALID,
+             "row-register triangular solve: l out of range");
   if (rows <= 0) {
     if (colsum) {
       hipLaunchKernelGGL(zero_doubles_kernel, dim3(static_cast<unsigned>(ceil_div(l, 256))), dim3(256), 0, stream,
@@ -1442,28 +1476,28 @@ void launch_rinv_apply(int64_t rows, int l, T* Y, int64_t ld, const typename Com
   const int vec = (ld % 4 == 0 && (reinterpret_cast<uintptr_t>(Y) % (4 * sizeof(T))) == 0) ? 1 : 0;
   const int64_t ntiles = ceil_div(rows, 16);
   const int64_t want = ceil_div(ntiles, 4);
-  const int64_t grid = want < kApplyParts ? want : kApplyParts;
+  const int64_t grid = want < kRowsTrsmParts ? want : kRowsTrsmParts;
   double* part = colsum ? work : nullptr;
   const int TT = pad16(l) / 16;
   if constexpr (sizeof(C) == 8) {
-    if (TT <= 4) rinv_apply_launch<T, C, 4>(rows, l, Y, ld, vec, Xf, part, grid, stream);
-    else rinv_apply_launch<T, C, 8>(rows, l, Y, ld, vec, Xf, part, grid, stream);
+    if (TT <= 4) trsm_rows_launch<T, C, 4>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else trsm_rows_launch<T, C, 8>(rows, l, Y, ld, vec, Rf, part, grid, stream);
   } else {
-    if (TT <= 4) rinv_apply_launch<T, C, 4>(rows, l, Y, ld, vec, Xf, part, grid, stream);
-    else if (TT <= 8) rinv_apply_launch<T, C, 8>(rows, l, Y, ld, vec, Xf, part, grid, stream);
-    else if (TT <= 12) rinv_apply_launch<T, C, 12>(rows, l, Y, ld, vec, Xf, part, grid, stream);
-    else if (TT <= 16) rinv_apply_launch<T, C, 16>(rows, l, Y, ld, vec, Xf, part, grid, stream);
-    else if (TT <= 18) rinv_apply_launch<T, C, 18>(rows, l, Y, ld, vec, Xf, part, grid, stream);
-    else rinv_apply_launch<T, C, 20>(rows, l, Y, ld, vec, Xf, part, grid, stream);
+    if (TT <= 4) trsm_rows_launch<T, C, 4>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else if (TT <= 8) trsm_rows_launch<T, C, 8>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else if (TT <= 12) trsm_rows_launch<T, C, 12>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else if (TT <= 16) trsm_rows_launch<T, C, 16>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else if (TT <= 18) trsm_rows_launch<T, C, 18>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else trsm_rows_launch<T, C, 20>(rows, l, Y, ld, vec, Rf, part, grid, stream);
   }
   if (colsum) {
     hipLaunchKernelGGL(colpart_reduce_kernel, dim3(l), dim3(256), 0, stream, static_cast<int>(grid), l, work, colsum);
     ISVD_LAUNCH_CHECK();
   }
 }
-template void launch_rinv_apply<double>(int64_t, int, double*, int64_t, const double*, double*, double*, hipStream_t);
-template void launch_rinv_apply<float>(int64_t, int, float*, int64_t, const float*, double*, double*, hipStream_t);
-template void launch_rinv_apply<bf16>(int64_t, int, bf16*, int64_t, const float*, double*, double*, hipStream_t);
+template void launch_trsm_rows<double>(int64_t, int, double*, int64_t, const double*, double*, double*, hipStream_t);
+template void launch_trsm_rows<float>(int64_t, int, float*, int64_t, const float*, double*, double*, hipStream_t);
+template void launch_trsm_rows<bf16>(int64_t, int, bf16*, int64_t, const float*, double*, double*, hipStream_t);
 
 void launch_upper_mult(int l, const double* A, const double* B, double* Cm, int64_t ld, hipStream_t stream) {
   const int lp = pad16(l);

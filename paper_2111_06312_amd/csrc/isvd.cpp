@@ -11,6 +11,7 @@
 // free:  |M v_i - s_i u_i| = column i of [Y | Qr] [U_R; -Z_R S].
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <type_traits>
 #include <vector>
 
@@ -28,7 +29,7 @@ struct SvdState {
   DevBuf qc, w, qr, y;
   // small FP64 matrices (padded lp x lp, ld lp)
   DevBuf G, R1, R2, Rc, Rtmp, Rcc, cs_work, sum_c, sum_r, Dc, flag, UR, ZR, sig, jac_work, rhs, left2, right2, gram_work, cn_work, sweeps;
-  DevBuf Rc64, Dc64, X64, Xf;   // explicit-inverse path of the orthonormalisation
+  DevBuf Rc64, Dc64, Xf;   // row-register triangular solve: FP64 factor outputs, packed operands
   int iterations = 0, applies = 0, bf16_iterations = 0, checks = 0, fallback = 0, ritz_steps = 0;
   double residual = -1.0;
   bool have_ritz = false;
@@ -45,18 +46,18 @@ struct SvdState {
 
 // CholeskyQR2 of Y in place; Rout (optional) receives R2 R1; colsum (optional,
 // l doubles) receives 1^T Q of the stored result.
-// Y <- Y R^-1 for the factor just computed: through the explicit FP64 inverse
-// (MFMA, rows independent) when l allows, else by tiled substitution.
+// Y <- Y R^-1 for the factor just computed: forward substitution with the
+// block's rows in registers (MFMA) when l allows, else the LDS-tiled version.
 template <typename T>
-void apply_rinv(SvdState& st, T* Y, int64_t rows, const double* R, bool use_inv, double* colsum,
+void apply_rinv(SvdState& st, T* Y, int64_t rows, const double* R, bool rows_path, double* colsum,
                 hipStream_t stream) {
   using C = typename ComputeOf<T>::type;
   const int l = st.l;
-  if (colsum) st.cs_work.ensure(std::max(trsm_colsum_workspace(l), rinv_apply_workspace(l)) * sizeof(double));
-  if (use_inv) {
-    launch_rinv_prepare<C>(l, R, st.Dc64.as<double>(), st.X64.as<double>(), st.Xf.as<C>(), stream);
-    launch_rinv_apply<T>(rows, l, Y, st.ld, st.Xf.as<C>(), colsum, colsum ? st.cs_work.as<double>() : nullptr,
-                         stream);
+  if (colsum) st.cs_work.ensure(std::max(trsm_colsum_workspace(l), trsm_rows_workspace(l)) * sizeof(double));
+  if (rows_path) {
+    launch_trsm_rows_pack<C>(l, R, st.Dc64.as<double>(), st.Xf.as<C>(), stream);
+    launch_trsm_rows<T>(rows, l, Y, st.ld, st.Xf.as<C>(), colsum, colsum ? st.cs_work.as<double>() : nullptr,
+                        stream);
   } else {
     launch_trsm_tall<T>(rows, l, Y, st.ld, st.Rcc.as<C>(), st.Dc.as<C>(), colsum,
                         colsum ? st.cs_work.as<double>() : nullptr, stream);
@@ -68,18 +69,14 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* cols
                     int npass = 2) {
   using C = typename ComputeOf<T>::type;
   const int l = st.l, lp = st.lp;
-  // The explicit inverse is not backward stable (its error grows with
-  // kappa(R) u of the compute type); BF16 blocks, whose own rounding is of
-  // that size, keep the substitution so their phase is not cut short.
-  const bool use_inv = !std::is_same<T, bf16>::value && l <= rinv_apply_max_l(static_cast<int>(sizeof(C)));
+  const bool use_inv = l <= trsm_rows_max_l(static_cast<int>(sizeof(C)));
   st.G.ensure(static_cast<size_t>(l) * l * sizeof(double));
   st.R1.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
   st.R2.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
   if (use_inv) {
     st.Rc64.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
     st.Dc64.ensure(static_cast<size_t>(lp) * 16 * sizeof(double));
-    st.X64.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
-    st.Xf.ensure(rinv_packed_elems(l) * sizeof(C));
+    st.Xf.ensure(trsm_rows_packed_elems(l) * sizeof(C));
   } else {
     st.Rcc.ensure(static_cast<size_t>(lp) * lp * sizeof(C));
     st.Dc.ensure(static_cast<size_t>(lp) * 16 * sizeof(C));
@@ -235,6 +232,9 @@ void ensure_blocks(SvdState& st) {
 // decays about geometrically, so the rate seen between the last two checks
 // predicts how many more iterations reach `tol`; the next check is placed at
 // 90% of that distance (at least 1 and at most 32 iterations ahead).
+constexpr int kFirstCheck = 2;    // iterations before the first residual check
+constexpr int kMaxCheckGap = 48;  // most iterations between two checks
+
 struct CheckSchedule {
   int every = 0;
   int next = 0;
@@ -242,7 +242,7 @@ struct CheckSchedule {
   double last_rho = -1.0;
   int plan(int t, double rho, double tol) {
     if (every > 0) return next = t + every;
-    int gap = 1;
+    int gap = 4;   // after the first check: the early decay is not yet geometric
     if (last_t >= 0 && rho > 0.0 && last_rho > rho) {
       const double rate = std::pow(rho / last_rho, 1.0 / (t - last_t));
       const double need = std::log(tol / rho) / std::log(rate);
@@ -250,23 +250,23 @@ struct CheckSchedule {
     } else if (last_t >= 0) {
       gap = 2 * (t - last_t);
     }
-    gap = gap < 1 ? 1 : (gap > 32 ? 32 : gap);
+    gap = gap < 1 ? 1 : (gap > kMaxCheckGap ? kMaxCheckGap : gap);
     last_t = t;
     last_rho = rho;
     return next = t + gap;
   }
 };
 
-// stall_ratio > 0: also stop (returning 2) when a check improves rho by less
-// than that factor over the previous check -- the precision floor of the
-// block storage has been reached.
+// stall_rate > 0: also stop (returning 2) when rho has fallen by less than a
+// factor stall_rate per iteration since the previous check -- the precision
+// floor of the block storage has been reached.
 template <typename T>
 int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, double tol, bool fixed, int t0,
-              hipStream_t stream, double stall_ratio = 0.0, int phase_cap = 0) {
+              hipStream_t stream, double stall_rate = 0.0, int phase_cap = 0) {
   const int l = st.l;
   CheckSchedule sched;
   sched.every = prm->check_every > 0 ? prm->check_every : 0;
-  sched.next = t0;
+  sched.next = t0 + (sched.every > 0 ? 0 : kFirstCheck);
   // 1^T Q of the blocks fed to the NE products come from the orthonormaliser
   const bool ne = op->form == ISVD_FORM_NE;
   if (ne) {
@@ -284,7 +284,10 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
         st.iterations = t - 1;
         return 1;
       }
-      if (stall_ratio > 0.0 && sched.last_rho > 0.0 && st.residual > stall_ratio * sched.last_rho) {
+      // precision floor: less than (1 - stall_rate) improvement per iteration
+      // since the previous check (checks near the target can be 1-3 iterations apart)
+      if (stall_rate > 0.0 && sched.last_rho > 0.0 && sched.last_t >= 0 &&
+          st.residual > sched.last_rho * std::pow(stall_rate, static_cast<double>((t - 1) - sched.last_t))) {
         st.iterations = t - 1;
         return 2;
       }
@@ -363,7 +366,7 @@ isvd_status svd_bf16(isvd_operator* op, const isvd_svd_params* prm, void* U, int
   }
   // BF16 until rho <= fp32_switch_tol, then widen Qc and continue in FP32.
   const int ok16 = run_phase<bf16>(st, op, prm, prm->fp32_switch_tol, false, 0, stream,
-                                  prm->bf16_max_iter > 0 ? 0.0 : 0.9, prm->bf16_max_iter);
+                                  prm->bf16_max_iter > 0 ? 0.0 : 0.98, prm->bf16_max_iter);
   if (!ok16) {
     st.bf16_iterations = st.iterations + 1;
     finalize<bf16, float>(st, op, U, ldu, S, V, ldv, stream);

@@ -146,8 +146,9 @@ isvd_status isvd_matmul_block(isvd_operator* op, int transpose, const void* Y, i
  *              dimension ld_omega), used verbatim.
  *  fp32_switch_tol : BF16 operators only; when > 0 the iteration continues
  *              in FP32 once rho <= fp32_switch_tol, or once rho has fallen by
- *              less than 2% per iteration since the previous check (the BF16
- *              rounding floor; BF16 alone cannot reach small residuals), or
+ *              less than 2% per iteration since the previous check, after at
+ *              least 10 BF16 iterations (the BF16 rounding floor; BF16 alone
+ *              cannot reach small residuals), or
  *              after bf16_max_iter iterations when that is > 0 (which replaces
  *              the 2% rule).  U and V are float for BF16 operators. */
 typedef struct {

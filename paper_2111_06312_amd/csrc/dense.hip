@@ -617,8 +617,61 @@ __device__ inline void diag_tile(const TileStore& W, int J, double* S, double* X
   }
 }
 
+// The same in registers: lane c (of each 16-lane group) holds column c of the
+// tile, pivots and row broadcasts go through 16-lane shuffles.  Group g then
+// forms rows g, g+4, g+8, g+12 of X = R^-1 (X R = I solved along each row,
+// every finished entry broadcast to the lanes of the later columns).
+__device__ inline void diag_tile_regs(const TileStore& W, int J, double* X, const double* refd, double rel_tol,
+                                      int lane, int* bad) {
+  const int c = lane & 15, g = lane >> 4;
+  double s[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s[i] = (i <= c) ? W.at(J, J, i, c) : 0.0;
+  int mybad = 0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double d = __shfl(s[j], j, 16);
+    if (!(d > rel_tol * refd[J * 16 + j]) || !isfinite(d)) mybad = 1;
+    const double r = sqrt(d > 0.0 ? d : 1e-300);
+    const double ri = 1.0 / r;
+    if (c == j) s[j] = r;
+    else if (c > j) s[j] *= ri;
+#pragma unroll
+    for (int a = j + 1; a < 16; ++a) {
+      const double t = __shfl(s[j], a, 16);
+      if (c >= a) s[a] -= t * s[j];
+    }
+  }
+  // lane c: s[i] = R[i][c] for i <= c
+  double rcc = 1.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+    if (i == c) rcc = s[i];
+  const double rinv_c = 1.0 / rcc;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int i = g + 4 * p;
+    double acc = 0.0, xval = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      double x = 0.0;
+      if (c == jj && jj >= i) x = ((jj == i ? 1.0 : 0.0) - acc) * rinv_c;
+      const double xb = __shfl(x, jj, 16);
+      if (c == jj) xval = x;
+      if (c > jj && jj >= i) acc += xb * s[jj];
+    }
+    X[i * 16 + c] = xval;
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) W.at(J, J, i, c) = (i <= c) ? s[i] : 0.0;
+  }
+  if (mybad) *bad = 1;
+  wave_lds_sync();
+}
+
 template <typename C>
-__global__ __launch_bounds__(1024) void cholesky_kernel(int l, const double* G, int64_t ldg, double shift,
+__global__ __launch_bounds__(512) void cholesky_kernel(int l, const double* G, int64_t ldg, double shift,
                                                         double rel_tol, double* R64, C* Rc, C* Dc, int* flag) {
   extern __shared__ double chol_lds[];
   const int lp = pad16(l), T = lp / 16;
@@ -646,14 +699,28 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(int l, const double* G, 
   }
   if (tid == 0) bad = 0;
   __syncthreads();
-  for (int J = 0; J < T; ++J) {
-    if (wave == 0) {
-      int mybad = 0;
-      diag_tile(W, J, S, X, refd, rel_tol, lane, &mybad);
-      if (mybad && lane == 0) bad = 1;
-      for (int e = lane; e < 256; e += 64) Dc[J * 256 + e] = static_cast<C>(X[e]);
+  // one trailing tile: W_KK2 -= R_JK^T R_JK2
+  auto trail = [&](int J, int K, int K2) {
+    v4d acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = W.at(K, K2, drow<double>(lk, r), li);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int kr = kk * 4 + lk;
+      acc = mfma4(-W.at(J, K, kr, li), W.at(J, K2, kr, li), acc);
     }
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) W.at(K, K2, drow<double>(lk, r), li) = acc[r];
+  };
+  auto factor_diag = [&](int J) {
+    int mybad = 0;
+    diag_tile_regs(W, J, X, refd, rel_tol, lane, &mybad);
+    if (mybad && lane == 0) bad = 1;
+    for (int e = lane; e < 256; e += 64) Dc[J * 256 + e] = static_cast<C>(X[e]);
+  };
+  if (wave == 0) factor_diag(0);
+  __syncthreads();
+  for (int J = 0; J < T; ++J) {
     // panel: R_JK = (R_JJ^-1)^T W_JK for K > J
     for (int K = J + 1 + wave; K < T; K += nw) {
       v4d acc = {0.0, 0.0, 0.0, 0.0};
@@ -668,26 +735,28 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(int l, const double* G, 
       for (int r = 0; r < 4; ++r) W.at(J, K, drow<double>(lk, r), li) = acc[r];
     }
     __syncthreads();
-    // trailing update: W_KK' -= R_JK^T R_JK', J < K <= K'
+    if (J + 1 == T) break;
+    // trailing update W_KK' -= R_JK^T R_JK', J < K <= K'.  Lookahead: wave 0
+    // updates tile (J+1, J+1) first and factors it while the other waves
+    // update the rest.
     const int rem = T - J - 1;
     const int pairs = rem * (rem + 1) / 2;
-    for (int pi = wave; pi < pairs; pi += nw) {
-      int a_ = 0, q = pi;
-      while (q >= rem - a_) {
-        q -= rem - a_;
-        ++a_;
+    if (wave == 0) {
+      trail(J, J + 1, J + 1);
+      // the tile just written is read back by other lanes of this wave
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      factor_diag(J + 1);
+    } else {
+      for (int pi = wave; pi < pairs; pi += nw - 1) {
+        int a_ = 0, q = pi;
+        while (q >= rem - a_) {
+          q -= rem - a_;
+          ++a_;
+        }
+        trail(J, J + 1 + a_, J + 1 + a_ + q);
       }
-      const int K = J + 1 + a_, K2 = K + q;
-      v4d acc;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = W.at(K, K2, drow<double>(lk, r), li);
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int kr = kk * 4 + lk;
-        acc = mfma4(-W.at(J, K, kr, li), W.at(J, K2, kr, li), acc);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) W.at(K, K2, drow<double>(lk, r), li) = acc[r];
     }
     __syncthreads();
   }
@@ -1398,7 +1467,7 @@ void launch_cholesky(int l, const double* G, int64_t ldg, double shift, double r
                      C* Rc, C* Dinv_c, int* flag, hipStream_t stream) {
   const int T = pad16(l) / 16;
   const size_t lds = T <= kCholLdsMaxTiles ? static_cast<size_t>(T) * (T + 1) / 2 * 256 * sizeof(double) : 0;
-  hipLaunchKernelGGL((cholesky_kernel<C>), dim3(1), dim3(1024), lds, stream, l, G, ldg, shift, rel_tol,
+  hipLaunchKernelGGL((cholesky_kernel<C>), dim3(1), dim3(512), lds, stream, l, G, ldg, shift, rel_tol,
                      R64, Rc, Dinv_c, flag);
   ISVD_LAUNCH_CHECK();
 }

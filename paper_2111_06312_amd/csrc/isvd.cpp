@@ -233,6 +233,7 @@ void ensure_blocks(SvdState& st) {
 // predicts how many more iterations reach `tol`; the next check is placed at
 // 90% of that distance (at least 1 and at most 32 iterations ahead).
 constexpr int kFirstCheck = 2;    // iterations before the first residual check
+constexpr int kStallMinIter = 10; // iterations of a phase before a stall may end it
 constexpr int kMaxCheckGap = 48;  // most iterations between two checks
 
 struct CheckSchedule {
@@ -285,8 +286,10 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
         return 1;
       }
       // precision floor: less than (1 - stall_rate) improvement per iteration
-      // since the previous check (checks near the target can be 1-3 iterations apart)
-      if (stall_rate > 0.0 && sched.last_rho > 0.0 && sched.last_t >= 0 &&
+      // since the previous check (checks near the target can be 1-3 iterations
+      // apart); not in the first kStallMinIter iterations of the phase, where
+      // the worst triplet's residual can stand still while the basis rotates
+      if (stall_rate > 0.0 && sched.last_rho > 0.0 && sched.last_t >= 0 && (t - 1) - t0 >= kStallMinIter &&
           st.residual > sched.last_rho * std::pow(stall_rate, static_cast<double>((t - 1) - sched.last_t))) {
         st.iterations = t - 1;
         return 2;

@@ -275,26 +275,28 @@ __global__ __launch_bounds__(64 * kGramMaxWaves) void gram_partial_kernel(
 
 // C[a][b] = sum over row slices of the partial Gram tiles: 64 outputs per
 // block, four interleaved partial sums per output, combined in a fixed order.
+// For A^T A only entries a <= b are summed (the partial tiles are exactly
+// symmetric) and written to both (a, b) and (b, a).
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int nparts, const double* partial, int mp,
                                                           int pp, int same, double* C, int64_t ldc) {
   __shared__ double red[4][64];
   const int e = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 64 + e;
-  const bool ok = idx < static_cast<int64_t>(m) * p;
-  const int a = ok ? static_cast<int>(idx / p) : 0, b = ok ? static_cast<int>(idx % p) : 0;
-  int sa = a, sb = b;
-  if (same && (a >> 4) > (b >> 4)) {
-    sa = b;
-    sb = a;
-  }
+  const bool in = idx < static_cast<int64_t>(m) * p;
+  const int a = in ? static_cast<int>(idx / p) : 0, b = in ? static_cast<int>(idx % p) : 0;
+  const bool ok = in && (!same || a <= b);
   double s = 0.0;
   const int64_t stride = static_cast<int64_t>(mp) * pp;
-  const int64_t off = static_cast<int64_t>(sa) * pp + sb;
+  const int64_t off = static_cast<int64_t>(a) * pp + b;
   if (ok)
     for (int q = w; q < nparts; q += 4) s += partial[q * stride + off];
   red[w][e] = s;
   __syncthreads();
-  if (w == 0 && ok) C[static_cast<int64_t>(a) * ldc + b] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+  if (w == 0 && ok) {
+    const double v = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+    C[static_cast<int64_t>(a) * ldc + b] = v;
+    if (same && a != b) C[static_cast<int64_t>(b) * ldc + a] = v;
+  }
 }
 
 struct GramPlan {
@@ -970,16 +972,34 @@ constexpr int kRowsTrsmParts = 1024;
 // just before it is overwritten by Q_K.  With colpart, each block writes the
 // FP64 column sums of the values it stored (per wave in LDS, then in a fixed
 // order over the waves).
-template <typename T, typename C, int MT>
+template <typename T, typename C, int MT, bool STAGED>
 __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* Y, int64_t ld, int vec,
-                                                        const C* Rf, double* colpart) {
+                                                        const C* Rf_global, double* colpart) {
   using V = typename Acc4<C>::type;
   __shared__ double csw[4][16 * MT];
+  extern __shared__ __align__(16) unsigned char trsm_smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int TT = (l + 15) / 16;
   if (colpart) {
     for (int c = lane; c < 16 * MT; c += 64) csw[wave][c] = 0.0;
+  }
+  // STAGED: the packed factor (all TT (TT + 1) / 2 tiles) is copied to LDS once
+  // per workgroup, so each column tile's operands come at LDS latency
+  const C* Rf = Rf_global;
+  if constexpr (STAGED) {
+    C* lds = reinterpret_cast<C*>(trsm_smem);
+    const int n4 = TT * (TT + 1) / 2 * 256 / 4;
+    for (int f = threadIdx.x; f < n4; f += blockDim.x) {
+      if constexpr (std::is_same<C, float>::value)
+        reinterpret_cast<float4*>(lds)[f] = reinterpret_cast<const float4*>(Rf_global)[f];
+      else {
+        reinterpret_cast<double2*>(lds)[2 * f] = reinterpret_cast<const double2*>(Rf_global)[2 * f];
+        reinterpret_cast<double2*>(lds)[2 * f + 1] = reinterpret_cast<const double2*>(Rf_global)[2 * f + 1];
+      }
+    }
+    __syncthreads();
+    Rf = lds;
   }
   const int64_t ntiles = (rows + 15) / 16;
   for (int64_t rt = static_cast<int64_t>(blockIdx.x) * 4 + wave; rt < ntiles; rt += static_cast<int64_t>(gridDim.x) * 4) {
@@ -987,10 +1007,13 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* 
     const bool rok = row0 + li < rows;
     T* rowp = Y + (row0 + li) * ld;
     C q[MT][4];
+    C ynext[4];
+    load_tile_row<T, C>(rowp, 0, lk, l, rok, vec != 0, ynext);
 #pragma unroll 1
     for (int K = 0; K < TT; ++K) {
-      C y[4];
-      load_tile_row<T, C>(rowp, K, lk, l, rok, vec != 0, y);
+      C y[4] = {ynext[0], ynext[1], ynext[2], ynext[3]};
+      // tile K + 1 of these rows is read while tile K is solved
+      if (K + 1 < TT) load_tile_row<T, C>(rowp, K + 1, lk, l, rok, vec != 0, ynext);
       V acc[4];
       acc[0] = V{y[0], y[1], y[2], y[3]};
       acc[1] = acc[2] = acc[3] = V{0, 0, 0, 0};
@@ -1520,11 +1543,18 @@ void launch_trsm_rows_pack(int l, const double* R64, const double* Dinv64, C* Rf
 template void launch_trsm_rows_pack<double>(int, const double*, const double*, double*, hipStream_t);
 template void launch_trsm_rows_pack<float>(int, const double*, const double*, float*, hipStream_t);
 
+constexpr size_t kTrsmRowsMaxLds = 96 * 1024;
+
 template <typename T, typename C, int MT>
 void trsm_rows_launch(int64_t rows, int l, T* Y, int64_t ld, int vec, const C* Rf, double* colpart, int64_t grid,
                       hipStream_t stream) {
-  hipLaunchKernelGGL((trsm_rows_kernel<T, C, MT>), dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, rows, l,
-                     Y, ld, vec, Rf, colpart);
+  const size_t packed = trsm_rows_packed_elems(l) * sizeof(C);
+  if (packed <= kTrsmRowsMaxLds)
+    hipLaunchKernelGGL((trsm_rows_kernel<T, C, MT, true>), dim3(static_cast<unsigned>(grid)), dim3(256), packed,
+                       stream, rows, l, Y, ld, vec, Rf, colpart);
+  else
+    hipLaunchKernelGGL((trsm_rows_kernel<T, C, MT, false>), dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream,
+                       rows, l, Y, ld, vec, Rf, colpart);
   ISVD_LAUNCH_CHECK();
 }
 
@@ -1554,6 +1584,7 @@ void launch_trsm_rows(int64_t rows, int l, T* Y, int64_t ld, const typename Comp
   } else {
     if (TT <= 4) trsm_rows_launch<T, C, 4>(rows, l, Y, ld, vec, Rf, part, grid, stream);
     else if (TT <= 8) trsm_rows_launch<T, C, 8>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else if (TT <= 9) trsm_rows_launch<T, C, 9>(rows, l, Y, ld, vec, Rf, part, grid, stream);
     else if (TT <= 12) trsm_rows_launch<T, C, 12>(rows, l, Y, ld, vec, Rf, part, grid, stream);
     else if (TT <= 16) trsm_rows_launch<T, C, 16>(rows, l, Y, ld, vec, Rf, part, grid, stream);
     else if (TT <= 18) trsm_rows_launch<T, C, 18>(rows, l, Y, ld, vec, Rf, part, grid, stream);

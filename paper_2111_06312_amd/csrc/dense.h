@@ -88,8 +88,11 @@ size_t jacobi_workspace_doubles(int n);
 // A (n x n, FP64 row-major lda) = U diag(s) V^T; U, V n x n row-major (ld n), s descending.
 // V0 (optional, n x n orthogonal, ld n, may alias V): starting rotation for the
 // block-parallel path (64 < n <= 512), e.g. the previous V of a slowly changing A.
+// rel_tol > 0 (block-parallel path): a column pair counts as orthogonal once
+// |cos| <= rel_tol instead of n eps (singular vectors to about rel_tol).
 void launch_jacobi_svd(int n, const double* A, int64_t lda, double* U, double* s, double* V,
-                       double* work, int* sweeps_out, hipStream_t stream, const double* V0 = nullptr);
+                       double* work, int* sweeps_out, hipStream_t stream, const double* V0 = nullptr,
+                       double rel_tol = 0.0);
 
 // ---------------------------------------------------------------- misc
 

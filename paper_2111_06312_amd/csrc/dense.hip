@@ -976,6 +976,14 @@ template <typename T, typename C, int MT, bool STAGED>
 __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* Y, int64_t ld, int vec,
                                                         const C* Rf_global, double* colpart) {
   using V = typename Acc4<C>::type;
+  // FP32 blocks of at most 192 columns keep per-lane column sums of their rows
+  // in registers and reduce them once; otherwise each tile is reduced at once
+  constexpr bool REGSUM = std::is_same<C, float>::value && MT <= 12;
+  C csl[REGSUM ? MT : 1][4];
+#pragma unroll
+  for (int J = 0; J < (REGSUM ? MT : 1); ++J)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) csl[J][r] = C(0);
   __shared__ double csw[4][16 * MT];
   extern __shared__ __align__(16) unsigned char trsm_smem[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1040,7 +1048,17 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* 
           for (int r = 0; r < 4; ++r) q[J][r] = o[r];
         }
       store_tile_row<T, C>(rowp, K, lk, l, rok, vec != 0, o);
-      if (colpart) {
+      if constexpr (REGSUM) {
+        if (colpart) {
+#pragma unroll
+          for (int J = 0; J < MT; ++J)
+            if (J == K) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                if (rok && 16 * K + drow<C>(lk, r) < l) csl[J][r] += stored_as<T, C>(o[r]);
+            }
+        }
+      } else if (colpart) {
         double cs[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -1057,6 +1075,21 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* 
     }
   }
   if (colpart) {
+    if constexpr (REGSUM) {
+      // one reduction over the 16 rows of the lane groups, in FP64
+#pragma unroll
+      for (int J = 0; J < MT; ++J) {
+        if (J < TT) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double v = static_cast<double>(csl[J][r]);
+#pragma unroll
+            for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 64);
+            if (li == 0) csw[wave][16 * J + drow<C>(lk, r)] = v;
+          }
+        }
+      }
+    }
     __syncthreads();
     for (int col = threadIdx.x; col < l; col += blockDim.x)
       colpart[static_cast<int64_t>(blockIdx.x) * l + col] = (csw[0][col] + csw[1][col]) + (csw[2][col] + csw[3][col]);
@@ -1215,7 +1248,7 @@ constexpr int kBJThreads = 1024;
 
 template <int B>
 __global__ __launch_bounds__(kBJThreads) void bjacobi_round_kernel(int n, int nb, int round, int sweep, double* Wt,
-                                                                   double* Jt, int* flags) {
+                                                                   double* Jt, int* flags, double rel_tol) {
   if (flags[0]) return;
   extern __shared__ double bjs[];
   double* Ws = bjs;                                  // 2B x n
@@ -1234,7 +1267,8 @@ __global__ __launch_bounds__(kBJThreads) void bjacobi_round_kernel(int n, int nb
   if (threadIdx.x == 0) any_rot = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double tol = static_cast<double>(n) * 2.220446049250313e-16;
+  // rotate while |cos| of the column pair exceeds rel_tol (default n eps)
+  const double tol = rel_tol > 0.0 ? rel_tol : static_cast<double>(n) * 2.220446049250313e-16;
   constexpr int P = 2 * B;  // local players
   for (int r = 0; r < P - 1; ++r) {
     for (int k = wave; k < B; k += kBJThreads / 64) {
@@ -1613,7 +1647,7 @@ size_t jacobi_workspace_doubles(int n) {
 }
 
 void launch_jacobi_svd(int n, const double* A, int64_t lda, double* U, double* s, double* V, double* work,
-                       int* sweeps_out, hipStream_t stream, const double* V0) {
+                       int* sweeps_out, hipStream_t stream, const double* V0, double rel_tol) {
   ISVD_CHECK(n >= 1 && n <= kJacobiMaxN, ISVD_E_INVALID, "small svd: n out of range");
   if (n <= 64 || n > 512) {
     // one workgroup, pairs held in registers
@@ -1649,14 +1683,17 @@ void launch_jacobi_svd(int n, const double* A, int64_t lda, double* U, double* s
   for (int sweep = 0; sweep < kMaxSweeps && !done; ++sweep) {
     for (int r = 0; r < nbk - 1; ++r) {
       if (B == 16)
-        hipLaunchKernelGGL(bjacobi_round_kernel<16>, dim3(nbk / 2), dim3(kBJThreads), lds, stream, n, nbk, r, sweep, Wt, Jt, flags);
+        hipLaunchKernelGGL(bjacobi_round_kernel<16>, dim3(nbk / 2), dim3(kBJThreads), lds, stream, n, nbk, r, sweep, Wt, Jt, flags,
+                           rel_tol);
       else
-        hipLaunchKernelGGL(bjacobi_round_kernel<8>, dim3(nbk / 2), dim3(kBJThreads), lds, stream, n, nbk, r, sweep, Wt, Jt, flags);
+        hipLaunchKernelGGL(bjacobi_round_kernel<8>, dim3(nbk / 2), dim3(kBJThreads), lds, stream, n, nbk, r, sweep, Wt, Jt, flags,
+                           rel_tol);
     }
     hipLaunchKernelGGL(bjacobi_check_kernel, dim3(1), dim3(64), 0, stream, sweep, flags);
     ISVD_LAUNCH_CHECK();
-    // read the convergence flag after the first few sweeps, then every other sweep
-    if (sweep >= 3 && (sweep % 2 == 1)) {
+    // read the convergence flag after every sweep from the third on (a sweep
+    // costs far more than the host round trip)
+    if (sweep >= 2) {
       ISVD_HIP(hipMemcpyAsync(&done, flags, sizeof(int), hipMemcpyDeviceToHost, stream));
       ISVD_HIP(hipStreamSynchronize(stream));
     }

@@ -133,7 +133,13 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* cols
   }
 }
 
-void ritz(SvdState& st, hipStream_t stream) {
+template <typename T> constexpr double kRitzTol = 1e-10;
+template <> constexpr double kRitzTol<double> = 0.0;
+
+// rel_tol: pair-orthogonality threshold of the Jacobi sweeps (0: n eps).
+// Blocks stored in FP32 or BF16 carry rounding of 1e-7 and more, so their
+// Ritz vectors need no more than 1e-10.
+void ritz(SvdState& st, hipStream_t stream, double rel_tol = 0.0) {
   const int l = st.l, lp = st.lp;
   st.UR.ensure(static_cast<size_t>(l) * l * sizeof(double));
   st.ZR.ensure(static_cast<size_t>(l) * l * sizeof(double));
@@ -144,7 +150,7 @@ void ritz(SvdState& st, hipStream_t stream) {
   // rotation Z_R nearly diagonalises the new R's columns: start the sweeps there
   launch_jacobi_svd(l, st.Rc.as<double>(), lp, st.UR.as<double>(), st.sig.as<double>(), st.ZR.as<double>(),
                     st.jac_work.as<double>(), st.sweeps.as<int>(), stream,
-                    st.zr_valid ? st.ZR.as<double>() : nullptr);
+                    st.zr_valid ? st.ZR.as<double>() : nullptr, rel_tol);
   st.have_ritz = true;
   st.zr_valid = true;
   st.ritz_steps++;
@@ -303,7 +309,7 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
     if (!fixed && t >= prm->max_iter) {
       // out of iterations: return the triplets of the last finished iteration
       if (st.ritz_iter != t - 1 && t >= 1) {
-        ritz(st, stream);
+        ritz(st, stream, kRitzTol<T>);
         st.ritz_iter = t - 1;
       }
       st.iterations = t - 1;
@@ -324,13 +330,13 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
     std::swap(st.qc.bytes, st.w.bytes);
     qc_sums = ne;
     if (fixed && t >= prm->q) {
-      ritz(st, stream);
+      ritz(st, stream, kRitzTol<T>);
       st.ritz_iter = t;
       st.iterations = t;
       return 1;
     }
     if (!fixed && ritz_now) {
-      ritz(st, stream);
+      ritz(st, stream, kRitzTol<T>);
       st.ritz_iter = t;
     }
   }

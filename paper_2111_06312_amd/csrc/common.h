@@ -102,6 +102,27 @@ __device__ inline float wave_sum(float v) {
   return v;
 }
 
+// Lane exchange within each row of 16 lanes through a DPP operand (no LDS
+// round trip).  Every lane of the wave must be active.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a row, returned to all of them: swap neighbours,
+// then pairs, then quads (half-row mirror), then halves (row mirror).  Each
+// step adds the same two operands on both partner lanes, so every lane of the
+// row ends with the same bits.
+__device__ inline double row16_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return v;
+}
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 

@@ -557,147 +557,166 @@ __device__ inline void wave_lds_sync() {
 }
 
 // Working storage of the blocked factorisation: the upper tiles (I <= J) of an
-// lp x lp matrix, either packed in LDS (small l) or in a global lp x lp array.
+// lp x lp matrix, either packed in LDS (small l) or in a global lp x lp array;
+// the choice is a template argument so LDS accesses compile to LDS
+// instructions (a run-time choice would make every access a generic one).
+template <bool kLds>
 struct TileStore {
-  double* lds;   // packed upper tiles, 256 doubles each, or null
-  double* glob;  // lp x lp row-major
+  double* p;  // kLds: packed upper tiles, 256 doubles each; else lp x lp row-major
   int T, lp;
   __device__ inline double& at(int I, int J, int r, int c) const {
-    if (lds) return lds[(static_cast<int64_t>(I) * T - static_cast<int64_t>(I) * (I - 1) / 2 + (J - I)) * 256 + r * 16 + c];
-    return glob[static_cast<int64_t>(I * 16 + r) * lp + J * 16 + c];
+    if constexpr (kLds) return p[(I * T - I * (I - 1) / 2 + (J - I)) * 256 + r * 16 + c];
+    return p[static_cast<int64_t>(I * 16 + r) * lp + J * 16 + c];
   }
 };
 
 constexpr int kCholLdsMaxTiles = 11;   // 66 packed tiles = 132 KB of LDS
 constexpr int kJacobiMaxNForChol = 1024;  // l <= 1024
 
-// One wave factors diagonal tile J (right-looking, in the scratch tile `S`)
-// and inverts its upper factor column by column into `X`.
-__device__ inline void diag_tile(const TileStore& W, int J, double* S, double* X, const double* refd,
-                                 double rel_tol, int lane, int* bad) {
-  for (int e = lane; e < 256; e += 64) S[e] = W.at(J, J, e >> 4, e & 15);
-  wave_lds_sync();
-  for (int j = 0; j < 16; ++j) {
-    const double ref = refd[J * 16 + j];
-    const double piv = S[j * 16 + j];
-    if ((!(piv > rel_tol * ref) || !isfinite(piv)) && lane == 0) *bad = 1;
-    const double r = sqrt(piv > 0.0 ? piv : 1e-300);
-    const double rinv = 1.0 / r;
-    wave_lds_sync();
-    if (lane > j && lane < 16) S[j * 16 + lane] *= rinv;
-    if (lane == j) S[j * 16 + j] = r;
-    wave_lds_sync();
-    // trailing update of the tile: S[a][b] -= R[j][a] R[j][b], j < a <= b
-    for (int e = lane; e < 256; e += 64) {
-      const int a = e >> 4, bb = e & 15;
-      if (a > j && bb >= a) S[e] -= S[j * 16 + a] * S[j * 16 + bb];
-    }
-    wave_lds_sync();
-  }
-  // X = R^-1: lane c solves R x = e_c by back substitution (x_i = 0 for i > c)
-  // reciprocals of the 16 pivots, one per lane, then back substitution by multiplication
-  if (lane < 16) X[lane * 16 + lane] = 1.0 / S[lane * 16 + lane];
-  wave_lds_sync();
-  if (lane < 16) {
-    const int c = lane;
-    double x[16];
-#pragma unroll
-    for (int i = 15; i >= 0; --i) {
-      double acc = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = i + 1; k < 16; ++k) acc -= S[i * 16 + k] * x[k];
-      x[i] = (i <= c) ? acc * X[i * 16 + i] : 0.0;
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int i = 0; i < 16; ++i) X[i * 16 + c] = x[i];
-  }
-  wave_lds_sync();
-  for (int e = lane; e < 256; e += 64) {
-    const int a = e >> 4, bb = e & 15;
-    W.at(J, J, a, bb) = (bb >= a) ? S[e] : 0.0;
+// Value of lane n of each 16-lane row, given to every lane of that row (DPP
+// row broadcast, one 64-bit move).  n must fold to a constant.
+template <int N>
+__device__ inline double row_bcast_n(double v) {
+  return __longlong_as_double(__builtin_amdgcn_mov_dpp(__double_as_longlong(v), 0x150 + N, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double row_bcast(double v, int n) {
+  switch (n) {
+    case 0: return row_bcast_n<0>(v);
+    case 1: return row_bcast_n<1>(v);
+    case 2: return row_bcast_n<2>(v);
+    case 3: return row_bcast_n<3>(v);
+    case 4: return row_bcast_n<4>(v);
+    case 5: return row_bcast_n<5>(v);
+    case 6: return row_bcast_n<6>(v);
+    case 7: return row_bcast_n<7>(v);
+    case 8: return row_bcast_n<8>(v);
+    case 9: return row_bcast_n<9>(v);
+    case 10: return row_bcast_n<10>(v);
+    case 11: return row_bcast_n<11>(v);
+    case 12: return row_bcast_n<12>(v);
+    case 13: return row_bcast_n<13>(v);
+    case 14: return row_bcast_n<14>(v);
+    default: return row_bcast_n<15>(v);
   }
 }
 
-// The same in registers: lane c (of each 16-lane group) holds column c of the
-// tile, pivots and row broadcasts go through 16-lane shuffles.  Group g then
-// forms rows g, g+4, g+8, g+12 of X = R^-1 (X R = I solved along each row,
-// every finished entry broadcast to the lanes of the later columns).
-__device__ inline void diag_tile_regs(const TileStore& W, int J, double* X, const double* refd, double rel_tol,
-                                      int lane, int* bad) {
-  const int c = lane & 15, g = lane >> 4;
+// The same in registers: lane c of each 16-lane row holds column c of the
+// tile (the four rows of the wave hold the same columns and compute the same
+// values); pivots and row entries reach the other lanes by row broadcasts.
+// Row j of the factor is W_j. / r_j; lane a's entry is formed from its
+// unscaled value with the same rounding lane a applies, so the update does
+// not wait for the scaling.  The column loop touches no memory and takes no
+// branch (selects only); lane c keeps its own pivot and checks it at the end.
+// X = R^-1 is then solved column by column (lane c: R x = e_c by back
+// substitution, each finished x_k folded into the remaining rows).
+template <bool kLds>
+__device__ __forceinline__ void diag_tile_regs(const TileStore<kLds>& W, int J, double* X, const double* refd,
+                                               double rel_tol, int lane, int* bad) {
+  const int c = lane & 15;
   double s[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) s[i] = (i <= c) ? W.at(J, J, i, c) : 0.0;
-  int mybad = 0;
+  const double ref_c = refd[J * 16 + c];
+  double d_c = 0.0, rinv_c = 0.0;  // lane c: pivot of column c and 1 / R[c][c]
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const double d = __shfl(s[j], j, 16);
-    if (!(d > rel_tol * refd[J * 16 + j]) || !isfinite(d)) mybad = 1;
-    const double r = sqrt(d > 0.0 ? d : 1e-300);
-    const double ri = 1.0 / r;
-    if (c == j) s[j] = r;
-    else if (c > j) s[j] *= ri;
+    const double d = row_bcast(s[j], j);
+    // 1/sqrt(d) from the hardware estimate and two Newton-Raphson steps
+    // (y <- y + y (1 - d y^2) / 2, error squared each step), r = d / sqrt(d)
+    const double dd = d > 0.0 ? d : 1e-300;
+    double ri = __builtin_amdgcn_rsq(dd);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) ri = fma(0.5 * ri, fma(-dd * ri, ri, 1.0), ri);
+    const double r = dd * ri;
+    const double rc = s[j] * ri;  // R[j][c]
+    // lanes c < a update s[a] too: entries below the diagonal are never read
+    // (broadcasts take s[i] from lanes k > i) and are zeroed on the way out
 #pragma unroll
     for (int a = j + 1; a < 16; ++a) {
-      const double t = __shfl(s[j], a, 16);
-      if (c >= a) s[a] -= t * s[j];
+      const double t = row_bcast(s[j], a) * ri;  // R[j][a]
+      s[a] = fma(-t, rc, s[a]);
     }
+    s[j] = (c == j) ? r : ((c > j) ? rc : s[j]);
+    d_c = (c == j) ? d : d_c;
+    rinv_c = (c == j) ? ri : rinv_c;
+    __builtin_amdgcn_sched_barrier(0);  // keep the broadcasts of later columns from piling up
   }
-  // lane c: s[i] = R[i][c] for i <= c
-  double rcc = 1.0;
+  if (lane < 16 && (!(d_c > rel_tol * ref_c) || !isfinite(d_c))) *bad = 1;
+  // lane c: s[i] = R[i][c] for i <= c, 0 below.  All four rows store the
+  // same values (no branch).
+  double acc[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i)
-    if (i == c) rcc = s[i];
-  const double rinv_c = 1.0 / rcc;
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0;
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const int i = g + 4 * p;
-    double acc = 0.0, xval = 0.0;
+  for (int k = 15; k >= 0; --k) {
+    const double xk = ((k == c ? 1.0 : 0.0) - acc[k]) * row_bcast(rinv_c, k);
+    X[k * 16 + c] = xk;
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-      double x = 0.0;
-      if (c == jj && jj >= i) x = ((jj == i ? 1.0 : 0.0) - acc) * rinv_c;
-      const double xb = __shfl(x, jj, 16);
-      if (c == jj) xval = x;
-      if (c > jj && jj >= i) acc += xb * s[jj];
-    }
-    X[i * 16 + c] = xval;
+    for (int i = 0; i < k; ++i) acc[i] = fma(row_bcast(s[i], k), xk, acc[i]);  // R[i][k] x_k
+    __builtin_amdgcn_sched_barrier(0);
   }
-  if (g == 0) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) W.at(J, J, i, c) = (i <= c) ? s[i] : 0.0;
-  }
-  if (mybad) *bad = 1;
+  for (int i = 0; i < 16; ++i) W.at(J, J, i, c) = (i <= c) ? s[i] : 0.0;
   wave_lds_sync();
 }
 
-template <typename C>
-__global__ __launch_bounds__(512) void cholesky_kernel(int l, const double* G, int64_t ldg, double shift,
+constexpr int kCholThreads = 512;
+
+template <typename C, bool kLds>
+__global__ __launch_bounds__(kCholThreads) void cholesky_kernel(int l, const double* G, int64_t ldg, double shift,
                                                         double rel_tol, double* R64, C* Rc, C* Dc, int* flag) {
   extern __shared__ double chol_lds[];
   const int lp = pad16(l), T = lp / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  __shared__ double S[256], X[256];
+  __shared__ double X[256];
   __shared__ double refd[kJacobiMaxNForChol];
   __shared__ int bad;
-  TileStore W{T <= kCholLdsMaxTiles ? chol_lds : nullptr, R64, T, lp};
+  const TileStore<kLds> W{kLds ? chol_lds : R64, T, lp};
   for (int i = tid; i < lp; i += blockDim.x)
     refd[i] = i < l ? fabs(G[static_cast<int64_t>(i) * ldg + i] + shift) : 1.0;
-  // W = G + shift I on the upper tiles, identity on the padding
-  const int ntiles = T * (T + 1) / 2;
-  for (int64_t f = tid; f < static_cast<int64_t>(ntiles) * 256; f += blockDim.x) {
-    int I = 0, rem = static_cast<int>(f >> 8);
-    while (rem >= T - I) {
-      rem -= T - I;
-      ++I;
+  // W = G + shift I on the upper tiles, identity on the padding.  Thread tid
+  // takes elements tid, tid + N, ... (row-major, N threads); their (row,
+  // column) advance by (N / lp, N % lp) with one carry, so no division per
+  // element, and each batch of kLoadU loads is unconditional (clamped
+  // addresses) so the whole batch is in flight at once.
+  constexpr int kLoadU = 16;
+  const int stride_i = kCholThreads / lp, stride_j = kCholThreads - stride_i * lp;
+  auto advance = [&](int& i, int& j) {
+    i += stride_i;
+    j += stride_j;
+    if (j >= lp) {
+      j -= lp;
+      ++i;
     }
-    const int J = I + rem, r = (f >> 4) & 15, c = f & 15;
-    const int i = I * 16 + r, j = J * 16 + c;
-    double v = (i == j) ? 1.0 : 0.0;
-    if (i < l && j < l) v = G[static_cast<int64_t>(i) * ldg + j] + (i == j ? shift : 0.0);
-    W.at(I, J, r, c) = v;
+  };
+  // (A value select would let the compiler move each load into its own
+  // branch and wait for it there, so elements outside the matrix load a
+  // clamped address and are masked arithmetically: v = g m + a.  Elements
+  // with no place in the packed tiles are written to a junk slot.)
+  __shared__ double junk;
+  {
+    int ci = tid / lp, cj = tid - (tid / lp) * lp;
+    while (ci < lp) {
+      double v[kLoadU];
+      int ii[kLoadU], jj[kLoadU];
+#pragma unroll
+      for (int u = 0; u < kLoadU; ++u) {
+        ii[u] = ci;
+        jj[u] = cj;
+        const bool in = ci < l && cj < l;
+        const double gv = G[static_cast<int64_t>(ci < l ? ci : l - 1) * ldg + (cj < l ? cj : l - 1)];
+        v[u] = fma(gv, in ? 1.0 : 0.0, ci == cj ? (in ? shift : 1.0) : 0.0);
+        advance(ci, cj);
+      }
+#pragma unroll
+      for (int u = 0; u < kLoadU; ++u) {
+        const int i = ii[u] < lp ? ii[u] : 0, j = jj[u];
+        const bool keep = ii[u] < lp && (i >> 4) <= (j >> 4);
+        double* dst = keep ? &W.at(i >> 4, j >> 4, i & 15, j & 15) : &junk;
+        *dst = v[u];
+      }
+    }
   }
   if (tid == 0) bad = 0;
   __syncthreads();
@@ -715,9 +734,7 @@ __global__ __launch_bounds__(512) void cholesky_kernel(int l, const double* G, i
     for (int r = 0; r < 4; ++r) W.at(K, K2, drow<double>(lk, r), li) = acc[r];
   };
   auto factor_diag = [&](int J) {
-    int mybad = 0;
-    diag_tile_regs(W, J, X, refd, rel_tol, lane, &mybad);
-    if (mybad && lane == 0) bad = 1;
+    diag_tile_regs(W, J, X, refd, rel_tol, lane, &bad);
     for (int e = lane; e < 256; e += 64) Dc[J * 256 + e] = static_cast<C>(X[e]);
   };
   if (wave == 0) factor_diag(0);
@@ -762,14 +779,34 @@ __global__ __launch_bounds__(512) void cholesky_kernel(int l, const double* G, i
     }
     __syncthreads();
   }
-  // R64 and Rc: upper tiles of W, zeros below the diagonal
-  for (int64_t idx = tid; idx < static_cast<int64_t>(lp) * lp; idx += blockDim.x) {
-    const int i = static_cast<int>(idx / lp), j = static_cast<int>(idx % lp);
-    const int I = i >> 4, J = j >> 4;
-    const double v = (I <= J && (I < J || (i & 15) <= (j & 15))) ? W.at(I, J, i & 15, j & 15) : 0.0;
-    if (W.lds) R64[idx] = v;
-    else if (I > J) R64[idx] = 0.0;
-    Rc[idx] = static_cast<C>(v);
+  // R64 and Rc: upper tiles of W, zeros below the diagonal (same element
+  // walk; reads of W unconditional, from the mirrored tile below the
+  // diagonal, so a batch overlaps)
+  {
+    int ci = tid / lp, cj = tid - (tid / lp) * lp;
+    while (ci < lp) {
+      double v[kLoadU];
+      int ii[kLoadU], jj[kLoadU];
+#pragma unroll
+      for (int u = 0; u < kLoadU; ++u) {
+        const int i = ci < lp ? ci : lp - 1, j = cj;
+        ii[u] = ci;
+        jj[u] = cj;
+        const int I = i >> 4, J = j >> 4;
+        const bool up = I <= J;
+        const double w = W.at(up ? I : J, up ? J : I, (up ? i : j) & 15, (up ? j : i) & 15);
+        v[u] = w * ((I < J || (I == J && (i & 15) <= (j & 15))) ? 1.0 : 0.0);
+        advance(ci, cj);
+      }
+#pragma unroll
+      for (int u = 0; u < kLoadU; ++u) {
+        if (ii[u] < lp) {
+          const int64_t idx = static_cast<int64_t>(ii[u]) * lp + jj[u];
+          if (kLds || ii[u] > jj[u]) R64[idx] = v[u];
+          Rc[idx] = static_cast<C>(v[u]);
+        }
+      }
+    }
   }
   if (tid == 0) *flag = bad;
 }
@@ -1241,76 +1278,122 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(int n, const double* A, in
 // round-robin over blocks, one workgroup per block pair.  A workgroup loads
 // its 2B columns of W (and the matching rows of the rotation accumulator J)
 // into LDS and runs one full one-sided Jacobi sweep among them (2B-1 inner
-// rounds of B independent pairs, one wave per pair).  flags[0] = converged
-// (every later launch returns at once), flags[1 + s] = rotated in sweep s.
+// rounds of B independent pairs).  A pair is owned by one row of 16 lanes:
+// each lane holds PER >= ceil(n/16) elements of both columns in registers
+// for the inner round and the three 16-lane sums go through DPP, so an inner
+// round costs one LDS round trip and one barrier.  Columns sit in LDS with
+// stride 16 PER, zero beyond n, so every access is unconditional (rotating
+// zeros keeps them zero).  flags[0] = converged (every
+// later launch returns at once), flags[1 + s] = rotated in sweep s.
 
-constexpr int kBJThreads = 1024;
-
-template <int B>
-__global__ __launch_bounds__(kBJThreads) void bjacobi_round_kernel(int n, int nb, int round, int sweep, double* Wt,
-                                                                   double* Jt, int* flags, double rel_tol) {
+template <int B, int PER>
+__global__ __launch_bounds__(16 * B) void bjacobi_round_kernel(int n, int nb, int round, int sweep, double* Wt,
+                                                               double* Jt, int* flags, double rel_tol) {
   if (flags[0]) return;
   extern __shared__ double bjs[];
-  double* Ws = bjs;                                  // 2B x n
-  double* Js = bjs + static_cast<int64_t>(2 * B) * n;  // 2B x n
+  constexpr int NS = 16 * PER;    // LDS column stride
+  double* Ws = bjs;               // 2B columns
+  double* Js = bjs + 2 * B * NS;  // 2B columns
   __shared__ int any_rot;
   const int w = blockIdx.x;
   const int pa = (w == 0) ? 0 : ((w - 1 + round) % (nb - 1)) + 1;
   const int pb = ((nb - 2 - w + round) % (nb - 1)) + 1;
-  const int blk[2] = {pa, pb};
-  for (int64_t f = threadIdx.x; f < static_cast<int64_t>(2 * B) * n; f += blockDim.x) {
-    const int lc = static_cast<int>(f / n), i = static_cast<int>(f % n);
-    const int64_t gc = static_cast<int64_t>(blk[lc / B]) * B + (lc % B);
-    Ws[f] = Wt[gc * n + i];
-    Js[f] = Jt[gc * n + i];
+  // 2 PER elements of W and of J per thread, all loads in flight together
+  constexpr int kCopy = 2 * PER;
+  auto copy_index = [&](int j, int& f, int64_t& gidx, bool& in) {
+    f = threadIdx.x + j * 16 * B;
+    const int lc = f / NS, i = f - lc * NS;
+    gidx = (static_cast<int64_t>(lc < B ? pa : pb) * B + (lc & (B - 1))) * n + i;
+    in = i < n;
+  };
+  {
+    double wv[kCopy], jv[kCopy];
+#pragma unroll
+    for (int j = 0; j < kCopy; ++j) {
+      int f;
+      int64_t gi;
+      bool in;
+      copy_index(j, f, gi, in);
+      wv[j] = in ? Wt[gi] : 0.0;
+      jv[j] = in ? Jt[gi] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kCopy; ++j) {
+      const int f = threadIdx.x + j * 16 * B;
+      Ws[f] = wv[j];
+      Js[f] = jv[j];
+    }
   }
   if (threadIdx.x == 0) any_rot = 0;
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // rotate while |cos| of the column pair exceeds rel_tol (default n eps)
   const double tol = rel_tol > 0.0 ? rel_tol : static_cast<double>(n) * 2.220446049250313e-16;
-  constexpr int P = 2 * B;  // local players
+  constexpr int P = 2 * B;      // local players
+  constexpr bool kPreJ = PER <= 20;  // J rows loaded with W's (register budget)
+  const int k = threadIdx.x >> 4, g = threadIdx.x & 15;
+  int rot = 0;
   for (int r = 0; r < P - 1; ++r) {
-    for (int k = wave; k < B; k += kBJThreads / 64) {
-      const int a = (k == 0) ? 0 : ((k - 1 + r) % (P - 1)) + 1;
-      const int b = ((P - 2 - k + r) % (P - 1)) + 1;
-      double* wa = Ws + static_cast<int64_t>(a) * n;
-      double* wb = Ws + static_cast<int64_t>(b) * n;
-      double al = 0.0, be = 0.0, ga = 0.0;
-      for (int i = lane; i < n; i += 64) {
-        const double x = wa[i], y = wb[i];
-        al += x * x;
-        be += y * y;
-        ga += x * y;
+    const int a = (k == 0) ? 0 : ((k - 1 + r) % (P - 1)) + 1;
+    const int b = ((P - 2 - k + r) % (P - 1)) + 1;
+    double* wa = Ws + a * NS + g;
+    double* wb = Ws + b * NS + g;
+    double* ja = Js + a * NS + g;
+    double* jb = Js + b * NS + g;
+    double x[PER], y[PER], u[PER], v[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      x[e] = wa[16 * e];
+      y[e] = wb[16 * e];
+      if (kPreJ) {
+        u[e] = ja[16 * e];
+        v[e] = jb[16 * e];
       }
-      al = wave_sum(al);
-      be = wave_sum(be);
-      ga = wave_sum(ga);
-      if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t);
-        const double sn = c * t;
-        double* ja = Js + static_cast<int64_t>(a) * n;
-        double* jb = Js + static_cast<int64_t>(b) * n;
-        for (int i = lane; i < n; i += 64) {
-          const double x = wa[i], y = wb[i];
-          wa[i] = c * x - sn * y;
-          wb[i] = sn * x + c * y;
-          const double u = ja[i], v = jb[i];
-          ja[i] = c * u - sn * v;
-          jb[i] = sn * u + c * v;
+    }
+    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      al += x[e] * x[e];
+      be += y[e] * y[e];
+      ga += x[e] * y[e];
+    }
+    al = row16_sum(al);
+    be = row16_sum(be);
+    ga = row16_sum(ga);
+    if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+      const double zeta = (be - al) / (2.0 * ga);
+      const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double c = 1.0 / sqrt(1.0 + t * t);
+      const double sn = c * t;
+      if (!kPreJ) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          u[e] = ja[16 * e];
+          v[e] = jb[16 * e];
         }
-        if (lane == 0) any_rot = 1;
       }
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        wa[16 * e] = c * x[e] - sn * y[e];
+        wb[16 * e] = sn * x[e] + c * y[e];
+        ja[16 * e] = c * u[e] - sn * v[e];
+        jb[16 * e] = sn * u[e] + c * v[e];
+      }
+      rot = 1;
     }
     __syncthreads();
   }
-  for (int64_t f = threadIdx.x; f < static_cast<int64_t>(2 * B) * n; f += blockDim.x) {
-    const int lc = static_cast<int>(f / n), i = static_cast<int>(f % n);
-    const int64_t gc = static_cast<int64_t>(blk[lc / B]) * B + (lc % B);
-    Wt[gc * n + i] = Ws[f];
-    Jt[gc * n + i] = Js[f];
+  if (rot) any_rot = 1;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kCopy; ++j) {
+    int f;
+    int64_t gi;
+    bool in;
+    copy_index(j, f, gi, in);
+    if (in) {
+      Wt[gi] = Ws[f];
+      Jt[gi] = Js[f];
+    }
   }
   if (threadIdx.x == 0 && any_rot) flags[1 + sweep] = 1;
 }
@@ -1524,8 +1607,12 @@ void launch_cholesky(int l, const double* G, int64_t ldg, double shift, double r
                      C* Rc, C* Dinv_c, int* flag, hipStream_t stream) {
   const int T = pad16(l) / 16;
   const size_t lds = T <= kCholLdsMaxTiles ? static_cast<size_t>(T) * (T + 1) / 2 * 256 * sizeof(double) : 0;
-  hipLaunchKernelGGL((cholesky_kernel<C>), dim3(1), dim3(512), lds, stream, l, G, ldg, shift, rel_tol,
-                     R64, Rc, Dinv_c, flag);
+  if (T <= kCholLdsMaxTiles)
+    hipLaunchKernelGGL((cholesky_kernel<C, true>), dim3(1), dim3(kCholThreads), lds, stream, l, G, ldg, shift,
+                       rel_tol, R64, Rc, Dinv_c, flag);
+  else
+    hipLaunchKernelGGL((cholesky_kernel<C, false>), dim3(1), dim3(kCholThreads), 0, stream, l, G, ldg, shift,
+                       rel_tol, R64, Rc, Dinv_c, flag);
   ISVD_LAUNCH_CHECK();
 }
 template void launch_cholesky<double>(int, const double*, int64_t, double, double, double*, double*, double*, int*, hipStream_t);
@@ -1677,18 +1764,31 @@ void launch_jacobi_svd(int n, const double* A, int64_t lda, double* U, double* s
   hipLaunchKernelGGL(bjacobi_init_kernel, dim3(static_cast<unsigned>(ceil_div(total, 256))), dim3(256), 0, stream, n, np,
                      A, lda, V0, Wt, Jt, flags, nflags);
   ISVD_LAUNCH_CHECK();
-  const size_t lds = static_cast<size_t>(4) * B * n * sizeof(double);
+  const int per = static_cast<int>(ceil_div(n, 16));
+  auto round_launch = [&](int r, int sweep) {
+    const dim3 grid(nbk / 2), block(16 * B);
+    // 2B columns of W and of J, stride 16 PER (PER: the template argument)
+    auto lds_of = [&](int PER) { return static_cast<size_t>(4) * B * 16 * PER * sizeof(double); };
+    if (B == 16) {
+      if (per <= 5)
+        hipLaunchKernelGGL((bjacobi_round_kernel<16, 5>), grid, block, lds_of(5), stream, n, nbk, r, sweep, Wt, Jt, flags, rel_tol);
+      else if (per <= 9)
+        hipLaunchKernelGGL((bjacobi_round_kernel<16, 9>), grid, block, lds_of(9), stream, n, nbk, r, sweep, Wt, Jt, flags, rel_tol);
+      else if (per <= 13)
+        hipLaunchKernelGGL((bjacobi_round_kernel<16, 13>), grid, block, lds_of(13), stream, n, nbk, r, sweep, Wt, Jt, flags, rel_tol);
+      else
+        hipLaunchKernelGGL((bjacobi_round_kernel<16, 19>), grid, block, lds_of(19), stream, n, nbk, r, sweep, Wt, Jt, flags, rel_tol);
+    } else {
+      if (per <= 26)
+        hipLaunchKernelGGL((bjacobi_round_kernel<8, 26>), grid, block, lds_of(26), stream, n, nbk, r, sweep, Wt, Jt, flags, rel_tol);
+      else
+        hipLaunchKernelGGL((bjacobi_round_kernel<8, 32>), grid, block, lds_of(32), stream, n, nbk, r, sweep, Wt, Jt, flags, rel_tol);
+    }
+  };
   constexpr int kMaxSweeps = 40;
   int done = 0;
   for (int sweep = 0; sweep < kMaxSweeps && !done; ++sweep) {
-    for (int r = 0; r < nbk - 1; ++r) {
-      if (B == 16)
-        hipLaunchKernelGGL(bjacobi_round_kernel<16>, dim3(nbk / 2), dim3(kBJThreads), lds, stream, n, nbk, r, sweep, Wt, Jt, flags,
-                           rel_tol);
-      else
-        hipLaunchKernelGGL(bjacobi_round_kernel<8>, dim3(nbk / 2), dim3(kBJThreads), lds, stream, n, nbk, r, sweep, Wt, Jt, flags,
-                           rel_tol);
-    }
+    for (int r = 0; r < nbk - 1; ++r) round_launch(r, sweep);
     hipLaunchKernelGGL(bjacobi_check_kernel, dim3(1), dim3(64), 0, stream, sweep, flags);
     ISVD_LAUNCH_CHECK();
     // read the convergence flag after every sweep from the third on (a sweep

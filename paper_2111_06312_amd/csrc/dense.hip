@@ -1117,67 +1117,84 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* 
       }
     }
   } else {
-    // wider blocks: the register budget allows one tile of look-ahead
+    // wider blocks (the register budget allows no more): one tile of
+    // look-ahead for Y, carried across row tiles; the factor fragments of a
+    // column tile are read kGroup at a time (clamped to valid tiles, so a
+    // group's loads are in flight together)
+    constexpr int kGroup = 4;
     const int64_t ntiles = (rows + 15) / 16;
-    for (int64_t rt = static_cast<int64_t>(blockIdx.x) * 4 + wave; rt < ntiles; rt += static_cast<int64_t>(gridDim.x) * 4) {
+    const int64_t tstride = static_cast<int64_t>(gridDim.x) * 4;
+    int64_t rt = static_cast<int64_t>(blockIdx.x) * 4 + wave;
+    C ynext[4] = {C(0), C(0), C(0), C(0)};
+    if (rows > 0) {
+      const int64_t r = (rt < ntiles ? rt : 0) * 16 + li;
+      load_tile_row<T, C>(Y + (r < rows ? r : rows - 1) * ld, 0, lk, l, true, vec != 0, ynext);
+    }
+    for (; rt < ntiles; rt += tstride) {
       const int64_t row0 = rt * 16;
       const bool rok = row0 + li < rows;
       T* rowp = Y + (row0 + li) * ld;
+      const T* crowp = Y + (rok ? row0 + li : rows - 1) * ld;
+      const int64_t nr = (rt + tstride < ntiles ? rt + tstride : rt) * 16 + li;
+      const T* nrowp = Y + (nr < rows ? nr : rows - 1) * ld;
       C q[MT][4];
-      C ynext[4];
-      load_tile_row<T, C>(rowp, 0, lk, l, rok, vec != 0, ynext);
-  #pragma unroll 1
+#pragma unroll 1
       for (int K = 0; K < TT; ++K) {
         C y[4] = {ynext[0], ynext[1], ynext[2], ynext[3]};
-        // tile K + 1 of these rows is read while tile K is solved
-        if (K + 1 < TT) load_tile_row<T, C>(rowp, K + 1, lk, l, rok, vec != 0, ynext);
+        if (K + 1 < TT) load_tile_row<T, C>(crowp, K + 1, lk, l, true, vec != 0, ynext);
+        else load_tile_row<T, C>(nrowp, 0, lk, l, true, vec != 0, ynext);
         V acc[4];
         acc[0] = V{y[0], y[1], y[2], y[3]};
         acc[1] = acc[2] = acc[3] = V{0, 0, 0, 0};
         const C* rk = Rf + static_cast<int64_t>(K * (K + 1) / 2) * 256 + 4 * lane;
-  #pragma unroll
-        for (int J = 0; J < MT; ++J) {
-          if (J >= K) continue;
-          C a[4];
-          load_frag4<C>(rk + 256 * J, a);
-  #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) acc[J & 3] = mfma4(-a[kk], q[J][kk], acc[J & 3]);
+#pragma unroll
+        for (int J0 = 0; J0 < MT; J0 += kGroup) {
+          if (J0 >= K) continue;
+          C a[kGroup][4];
+#pragma unroll
+          for (int g = 0; g < kGroup; ++g) load_frag4<C>(rk + 256 * (J0 + g < K ? J0 + g : J0), a[g]);
+#pragma unroll
+          for (int g = 0; g < kGroup; ++g) {
+            if (J0 + g >= MT || J0 + g >= K) continue;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) acc[g & 3] = mfma4(-a[g][kk], q[J0 + g][kk], acc[g & 3]);
+          }
         }
         const V sacc = (acc[0] + acc[1]) + (acc[2] + acc[3]);
         C d[4];
         load_frag4<C>(rk + 256 * K, d);
         V out = V{0, 0, 0, 0};
-  #pragma unroll
+#pragma unroll
         for (int kk = 0; kk < 4; ++kk) out = mfma4(d[kk], sacc[kk], out);
         C o[4] = {out[0], out[1], out[2], out[3]};
-  #pragma unroll
+#pragma unroll
         for (int J = 0; J < MT; ++J)
           if (J == K) {
-  #pragma unroll
+#pragma unroll
             for (int r = 0; r < 4; ++r) q[J][r] = o[r];
           }
         store_tile_row<T, C>(rowp, K, lk, l, rok, vec != 0, o);
         if constexpr (REGSUM) {
           if (colpart) {
-  #pragma unroll
+#pragma unroll
             for (int J = 0; J < MT; ++J)
               if (J == K) {
-  #pragma unroll
+#pragma unroll
                 for (int r = 0; r < 4; ++r)
                   if (rok && 16 * K + drow<C>(lk, r) < l) csl[J][r] += stored_as<T, C>(o[r]);
               }
           }
         } else if (colpart) {
           double cs[4];
-  #pragma unroll
+#pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int c = 16 * K + drow<C>(lk, r);
             cs[r] = (rok && c < l) ? static_cast<double>(stored_as<T, C>(o[r])) : 0.0;
-  #pragma unroll
+#pragma unroll
             for (int m = 1; m < 16; m <<= 1) cs[r] += __shfl_xor(cs[r], m, 64);
           }
           if (li == 0) {
-  #pragma unroll
+#pragma unroll
             for (int r = 0; r < 4; ++r) csw[wave][16 * K + drow<C>(lk, r)] += cs[r];
           }
         }

@@ -9,6 +9,9 @@
 #include "dense.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 namespace isvd {
@@ -1756,17 +1759,54 @@ template void launch_trsm_rows_pack<float>(int, const double*, const double*, fl
 
 constexpr size_t kTrsmRowsMaxLds = 96 * 1024;
 
+// Workgroups of `fn` (threads, dynamic LDS bytes) the current device holds at
+// once; cached per (kernel, LDS, device).
+int resident_workgroups(const void* fn, int threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, size_t, int>, int> cache;
+  int dev = 0;
+  ISVD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_tuple(fn, lds, dev);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  ISVD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds));
+  ISVD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int n = std::max(1, per_cu) * std::max(1, cus);
+  cache.emplace(key, n);
+  return n;
+}
+
+// The grid-stride row loop runs in one round of resident workgroups (a
+// partial second round would leave most of the chip idle at the end).
+// Returns the grid launched (the number of column-sum partials written).
 template <typename T, typename C, int MT>
-void trsm_rows_launch(int64_t rows, int l, T* Y, int64_t ld, int vec, const C* Rf, double* colpart, int64_t grid,
+int64_t trsm_rows_launch(int64_t rows, int l, T* Y, int64_t ld, int vec, const C* Rf, double* colpart, int64_t grid,
                       hipStream_t stream) {
-  const size_t packed = trsm_rows_packed_elems(l) * sizeof(C);
-  if (packed <= kTrsmRowsMaxLds)
-    hipLaunchKernelGGL((trsm_rows_kernel<T, C, MT, true>), dim3(static_cast<unsigned>(grid)), dim3(256), packed,
+  if constexpr (MT <= 12) {
+    const size_t packed = trsm_rows_packed_elems(l) * sizeof(C);
+    const bool staged = packed <= kTrsmRowsMaxLds;
+    const void* fn = staged ? reinterpret_cast<const void*>(&trsm_rows_kernel<T, C, MT, true>)
+                            : reinterpret_cast<const void*>(&trsm_rows_kernel<T, C, MT, false>);
+    const int64_t resident = resident_workgroups(fn, 256, staged ? packed : 0);
+    if (grid > resident) grid = resident;
+    if (staged)
+      hipLaunchKernelGGL((trsm_rows_kernel<T, C, MT, true>), dim3(static_cast<unsigned>(grid)), dim3(256), packed,
+                         stream, rows, l, Y, ld, vec, Rf, colpart);
+    else
+      hipLaunchKernelGGL((trsm_rows_kernel<T, C, MT, false>), dim3(static_cast<unsigned>(grid)), dim3(256), 0,
+                         stream, rows, l, Y, ld, vec, Rf, colpart);
+  } else {
+    // the factor is read from global memory (it does not fit in LDS)
+    const int64_t resident =
+        resident_workgroups(reinterpret_cast<const void*>(&trsm_rows_kernel<T, C, MT, false>), 256, 0);
+    if (grid > resident) grid = resident;
+    hipLaunchKernelGGL((trsm_rows_kernel<T, C, MT, false>), dim3(static_cast<unsigned>(grid)), dim3(256), 0,
                        stream, rows, l, Y, ld, vec, Rf, colpart);
-  else
-    hipLaunchKernelGGL((trsm_rows_kernel<T, C, MT, false>), dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream,
-                       rows, l, Y, ld, vec, Rf, colpart);
+  }
   ISVD_LAUNCH_CHECK();
+  return grid;
 }
 
 template <typename T>
@@ -1786,20 +1826,20 @@ void launch_trsm_rows(int64_t rows, int l, T* Y, int64_t ld, const typename Comp
   const int vec = (ld % 4 == 0 && (reinterpret_cast<uintptr_t>(Y) % (4 * sizeof(T))) == 0) ? 1 : 0;
   const int64_t ntiles = ceil_div(rows, 16);
   const int64_t want = ceil_div(ntiles, 4);
-  const int64_t grid = want < kRowsTrsmParts ? want : kRowsTrsmParts;
+  int64_t grid = want < kRowsTrsmParts ? want : kRowsTrsmParts;
   double* part = colsum ? work : nullptr;
   const int TT = pad16(l) / 16;
   if constexpr (sizeof(C) == 8) {
-    if (TT <= 4) trsm_rows_launch<T, C, 4>(rows, l, Y, ld, vec, Rf, part, grid, stream);
-    else trsm_rows_launch<T, C, 8>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    if (TT <= 4) grid = trsm_rows_launch<T, C, 4>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else grid = trsm_rows_launch<T, C, 8>(rows, l, Y, ld, vec, Rf, part, grid, stream);
   } else {
-    if (TT <= 4) trsm_rows_launch<T, C, 4>(rows, l, Y, ld, vec, Rf, part, grid, stream);
-    else if (TT <= 8) trsm_rows_launch<T, C, 8>(rows, l, Y, ld, vec, Rf, part, grid, stream);
-    else if (TT <= 9) trsm_rows_launch<T, C, 9>(rows, l, Y, ld, vec, Rf, part, grid, stream);
-    else if (TT <= 12) trsm_rows_launch<T, C, 12>(rows, l, Y, ld, vec, Rf, part, grid, stream);
-    else if (TT <= 16) trsm_rows_launch<T, C, 16>(rows, l, Y, ld, vec, Rf, part, grid, stream);
-    else if (TT <= 18) trsm_rows_launch<T, C, 18>(rows, l, Y, ld, vec, Rf, part, grid, stream);
-    else trsm_rows_launch<T, C, 20>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    if (TT <= 4) grid = trsm_rows_launch<T, C, 4>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else if (TT <= 8) grid = trsm_rows_launch<T, C, 8>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else if (TT <= 9) grid = trsm_rows_launch<T, C, 9>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else if (TT <= 12) grid = trsm_rows_launch<T, C, 12>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else if (TT <= 16) grid = trsm_rows_launch<T, C, 16>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else if (TT <= 18) grid = trsm_rows_launch<T, C, 18>(rows, l, Y, ld, vec, Rf, part, grid, stream);
+    else grid = trsm_rows_launch<T, C, 20>(rows, l, Y, ld, vec, Rf, part, grid, stream);
   }
   if (colsum) {
     hipLaunchKernelGGL(colpart_reduce_kernel, dim3(l), dim3(256), 0, stream, static_cast<int>(grid), l, work, colsum);

@@ -139,16 +139,45 @@ template <typename S> struct Pair<bf16, S> {
   }
 };
 
-// Columns c, c + 1 of a row (c even; zeros at and past `cols`).
+// Columns c, c + 1 of a row (c even; zeros at and past `cols`).  BF16 rows
+// are kept as loaded (the 32-bit word of a pair, or the zero-extended 16-bit
+// element, in v[0]) and widened by gram_widen at staging time: widening at
+// load time would make each load wait at once instead of under the MFMAs of
+// the current chunk.
 template <int VW, typename T, typename S>
 __device__ inline void gram_load(const T* row, int c, int cols, bool ok, S (&v)[VW]) {
-  if constexpr (VW == 1) {
+  if constexpr (std::is_same<T, bf16>::value) {
+    static_assert(sizeof(S) == 4, "BF16 rows are staged as FP32");
+    // paired BF16 rows have an even column count (gram_impl), so c < cols
+    // covers both elements of the word
+    uint32_t w = 0;
+    if constexpr (VW == 2) {
+      if (ok && c < cols) w = *reinterpret_cast<const uint32_t*>(row + c);
+    } else {
+      if (ok && c < cols) w = row[c].bits;
+    }
+    v[0] = __uint_as_float(w);
+    if constexpr (VW == 2) v[1] = S(0);
+  } else if constexpr (VW == 1) {
     v[0] = (ok && c < cols) ? static_cast<S>(Elem<T>::load(row + c)) : S(0);
   } else {
     v[0] = S(0);
     v[1] = S(0);
     if (ok && c + 1 < cols) Pair<T, S>::load(row + c, v[0], v[1]);
     else if (ok && c < cols) v[0] = static_cast<S>(Elem<T>::load(row + c));
+  }
+}
+
+// The staged values of what gram_load left in v (identity except for BF16).
+template <int VW, typename T, typename S>
+__device__ inline void gram_widen(const S (&v)[VW], S (&out)[VW]) {
+  if constexpr (std::is_same<T, bf16>::value) {
+    const uint32_t w = __float_as_uint(v[0]);
+    out[0] = __uint_as_float(w << 16);
+    if constexpr (VW == 2) out[1] = __uint_as_float(w & 0xffff0000u);
+  } else {
+#pragma unroll
+    for (int e = 0; e < VW; ++e) out[e] = v[e];
   }
 }
 
@@ -232,16 +261,22 @@ __global__ __launch_bounds__(64 * kGramMaxWaves) void gram_partial_kernel(
       S* da = dst + rl * ldsa + VW * lane;
 #pragma unroll
       for (int s = 0; s < CS; ++s)
-        if (VW * lane + 64 * VW * s < mpa)
+        if (VW * lane + 64 * VW * s < mpa) {
+          S w[VW];
+          gram_widen<VW, TA, S>(pa[j][s], w);
 #pragma unroll
-          for (int e = 0; e < VW; ++e) da[64 * VW * s + e] = pa[j][s][e];
+          for (int e = 0; e < VW; ++e) da[64 * VW * s + e] = w[e];
+        }
       if constexpr (!SAME) {
         S* db = dst + rb * ldsa + rl * ldsb + VW * lane;
 #pragma unroll
         for (int s = 0; s < CS; ++s)
-          if (VW * lane + 64 * VW * s < ppa)
+          if (VW * lane + 64 * VW * s < ppa) {
+            S w[VW];
+            gram_widen<VW, TB, S>(pb[j][s], w);
 #pragma unroll
-            for (int e = 0; e < VW; ++e) db[64 * VW * s + e] = pb[j][s][e];
+            for (int e = 0; e < VW; ++e) db[64 * VW * s + e] = w[e];
+          }
       }
     }
   };
@@ -389,7 +424,9 @@ template <typename TA, typename TB>
 void gram_impl(int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
                bool same, double* C, int64_t ldc, double* work, hipStream_t stream) {
   using S = typename GramStage<TA, TB>::type;
-  const bool paired = gram_pair_ok(A, lda) && (same || gram_pair_ok(B, ldb));
+  // BF16 pairs are loaded as one word without a tail case: even column counts only
+  const bool even_cols = (!std::is_same<TA, bf16>::value || m % 2 == 0) && (!std::is_same<TB, bf16>::value || p % 2 == 0);
+  const bool paired = gram_pair_ok(A, lda) && (same || gram_pair_ok(B, ldb)) && even_cols;
   const GramPlan g = plan_gram(rows, m, p, same, static_cast<int>(sizeof(S)), paired);
   if (paired) {
     switch (g.cs) {
@@ -943,22 +980,33 @@ __global__ void rfrag_pack_kernel(int lp, const double* R, const double* Dinv, C
 template <typename T, typename C> __device__ inline C stored_as(C v) { return v; }
 template <> __device__ inline float stored_as<bf16, float>(float v) { return bf16_to_float(float_to_bf16(v)); }
 
-// Elements drow(lk, 0..3) of tile K of one row (zeros past `cols` or when !ok).
+// Elements drow(lk, 0..3) of tile K of one row (zeros past `cols` or when !ok),
+// as loaded: for BF16 storage v[0], v[1] hold the two 32-bit words of the four
+// elements (packed in order) and widen_tile_row turns them into FP32 when the
+// tile is used, so a look-ahead load does not wait at the point it is issued.
 template <typename T, typename C>
 __device__ inline void load_tile_row(const T* rowp, int K, int lk, int cols, bool ok, bool vec, C (&v)[4]) {
+  if constexpr (std::is_same<T, bf16>::value) {
+    const int c0 = 16 * K + 4 * lk;   // drow<float>(lk, r) = 4 lk + r
+    if (ok && vec && c0 + 3 < cols) {
+      const uint2 q = *reinterpret_cast<const uint2*>(rowp + c0);
+      v[0] = __uint_as_float(q.x);
+      v[1] = __uint_as_float(q.y);
+    } else {
+      uint32_t e[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) e[r] = (ok && c0 + r < cols) ? rowp[c0 + r].bits : 0u;
+      v[0] = __uint_as_float(e[0] | (e[1] << 16));
+      v[1] = __uint_as_float(e[2] | (e[3] << 16));
+    }
+    v[2] = v[3] = C(0);
+    return;
+  }
   if constexpr (!std::is_same<C, double>::value) {
     const int c0 = 16 * K + 4 * lk;
     if (ok && vec && c0 + 3 < cols) {
-      if constexpr (std::is_same<T, float>::value) {
-        const float4 q = *reinterpret_cast<const float4*>(rowp + c0);
-        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-      } else {
-        const uint2 q = *reinterpret_cast<const uint2*>(rowp + c0);
-        v[0] = bf16_to_float(static_cast<uint16_t>(q.x & 0xffffu));
-        v[1] = bf16_to_float(static_cast<uint16_t>(q.x >> 16));
-        v[2] = bf16_to_float(static_cast<uint16_t>(q.y & 0xffffu));
-        v[3] = bf16_to_float(static_cast<uint16_t>(q.y >> 16));
-      }
+      const float4 q = *reinterpret_cast<const float4*>(rowp + c0);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
       return;
     }
   }
@@ -966,6 +1014,18 @@ __device__ inline void load_tile_row(const T* rowp, int K, int lk, int cols, boo
   for (int r = 0; r < 4; ++r) {
     const int c = 16 * K + drow<C>(lk, r);
     v[r] = (ok && c < cols) ? ld_as<C>(rowp + c) : C(0);
+  }
+}
+
+// The values of a tile row left by load_tile_row (identity except for BF16).
+template <typename T, typename C>
+__device__ inline void widen_tile_row(C (&v)[4]) {
+  if constexpr (std::is_same<T, bf16>::value) {
+    const uint32_t w0 = __float_as_uint(v[0]), w1 = __float_as_uint(v[1]);
+    v[0] = __uint_as_float(w0 << 16);
+    v[1] = __uint_as_float(w0 & 0xffff0000u);
+    v[2] = __uint_as_float(w1 << 16);
+    v[3] = __uint_as_float(w1 & 0xffff0000u);
   }
 }
 
@@ -1076,6 +1136,7 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* 
       for (int K = 0; K < MT; ++K) {
         if (K >= TT) continue;
         C y[4] = {yb[K][0], yb[K][1], yb[K][2], yb[K][3]};
+        widen_tile_row<T, C>(y);
         load_tile_row<T, C>(nrowp, K, lk, l, true, vec != 0, yb[K]);
         V acc[4];
         acc[0] = V{y[0], y[1], y[2], y[3]};
@@ -1144,6 +1205,7 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* 
 #pragma unroll 1
       for (int K = 0; K < TT; ++K) {
         C y[4] = {ynext[0], ynext[1], ynext[2], ynext[3]};
+        widen_tile_row<T, C>(y);
         if (K + 1 < TT) load_tile_row<T, C>(crowp, K + 1, lk, l, true, vec != 0, ynext);
         else load_tile_row<T, C>(nrowp, 0, lk, l, true, vec != 0, ynext);
         V acc[4];

@@ -150,7 +150,13 @@ isvd_status isvd_matmul_block(isvd_operator* op, int transpose, const void* Y, i
  *              least 10 BF16 iterations (the BF16 rounding floor; BF16 alone
  *              cannot reach small residuals), or
  *              after bf16_max_iter iterations when that is > 0 (which replaces
- *              the 2% rule).  U and V are float for BF16 operators. */
+ *              the 2% rule).  Without bf16_max_iter the FP32 phase first runs
+ *              as a probe until its residual decay predicts the iterations
+ *              still needed (taken 10% longer); while that prediction exceeds
+ *              the FP32 iterations a BF16 stretch needs at its end (10) by 8
+ *              or more, the blocks go back to BF16 for the difference (at most
+ *              as many iterations as done so far) and the probe repeats (at
+ *              most 3 times).  U and V are float for BF16 operators. */
 typedef struct {
   int k;
   int p;

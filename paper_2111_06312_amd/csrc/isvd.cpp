@@ -12,7 +12,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "operator.h"
@@ -35,14 +38,47 @@ struct SvdState {
   bool have_ritz = false;
   bool zr_valid = false;   // ZR holds the right rotation of an earlier Ritz step of this call
   int ritz_iter = -1;
+  int probe_need = -1;     // iterations to the tolerance predicted by a probing FP32 phase
+  // convergence trace (ISVD_TRACE set in the environment): per-triplet
+  // residuals and Ritz values of the last check, Ritz values of the one before
+  std::vector<double> rho_i, sig_k, prev_sig_k;
   void reset_counters() {
     iterations = applies = bf16_iterations = checks = fallback = ritz_steps = 0;
     residual = -1.0;
     have_ritz = false;
     zr_valid = false;
     ritz_iter = -1;
+    rho_i.clear();
+    sig_k.clear();
+    prev_sig_k.clear();
   }
 };
+
+bool trace_on() {
+  static const bool on = std::getenv("ISVD_TRACE") != nullptr;
+  return on;
+}
+
+// One stderr line per residual check: iteration, phase, max and quantiles of
+// the per-triplet residuals, Ritz values 1 and k, and the largest relative
+// change of the k Ritz values since the previous check.
+void trace_check(const SvdState& st, const char* phase, int t) {
+  if (!trace_on() || st.rho_i.empty()) return;
+  std::vector<double> r = st.rho_i;
+  std::sort(r.begin(), r.end());
+  const size_t k = r.size();
+  double dsig = -1.0;
+  if (st.prev_sig_k.size() == st.sig_k.size()) {
+    dsig = 0.0;
+    for (size_t i = 0; i < k; ++i)
+      if (st.sig_k[i] > 0.0) dsig = std::max(dsig, std::fabs(st.sig_k[i] - st.prev_sig_k[i]) / st.sig_k[i]);
+  }
+  std::fprintf(stderr,
+               "[isvd] %s t=%d rho max %.3e p50 %.3e p90 %.3e p99 %.3e | rho_1 %.3e rho_k %.3e | sig_1 %.6e sig_k %.6e "
+               "| max rel dsig %.3e\n",
+               phase, t, r[k - 1], r[k / 2], r[(9 * k) / 10], r[(99 * k) / 100], st.rho_i[0], st.rho_i[k - 1],
+               st.sig_k[0], st.sig_k[k - 1], dsig);
+}
 
 // CholeskyQR2 of Y in place; Rout (optional) receives R2 R1; colsum (optional,
 // l doubles) receives 1^T Q of the stored result.
@@ -177,9 +213,15 @@ double residual(SvdState& st, const T* Y, hipStream_t stream) {
   ISVD_HIP(hipMemcpyAsync(s.data(), st.sig.p, k * sizeof(double), hipMemcpyDeviceToHost, stream));
   ISVD_HIP(hipStreamSynchronize(stream));
   double rho = 0.0;
+  if (trace_on()) {
+    st.prev_sig_k = st.sig_k;
+    st.sig_k = s;
+    st.rho_i.assign(k, 0.0);
+  }
   for (int i = 0; i < k; ++i) {
     const double v = s[i] > 0.0 ? std::sqrt(a[i] + b[i]) / s[i] : INFINITY;
     rho = v > rho ? v : rho;
+    if (trace_on()) st.rho_i[i] = v;
   }
   st.checks++;
   return rho;
@@ -230,46 +272,64 @@ void ensure_blocks(SvdState& st) {
   st.Rc.ensure(static_cast<size_t>(st.lp) * st.lp * sizeof(double));
 }
 
-// Runs iterations in storage type T from the current Qc.  Returns 1 when the
-// Ritz triplets held in st satisfy the stopping rule of this phase (tolerance
-// `tol`, or the fixed count), 0 when max_iter was reached.
 // Iteration at which the next Rayleigh-Ritz step (and residual check) runs.
 // check_every > 0: a fixed stride.  check_every == 0: adaptive -- the residual
 // decays about geometrically, so the rate seen between the last two checks
 // predicts how many more iterations reach `tol`; the next check is placed at
-// 90% of that distance (at least 1 and at most 32 iterations ahead).
+// 90% of that distance (at least 1 and at most kMaxCheckGap iterations ahead).
 constexpr int kFirstCheck = 2;    // iterations before the first residual check
 constexpr int kStallMinIter = 10; // iterations of a phase before a stall may end it
 constexpr int kMaxCheckGap = 48;  // most iterations between two checks
+constexpr int kRateSpan = 4;      // iterations the decay rate is measured over, where checks allow
 
 struct CheckSchedule {
   int every = 0;
   int next = 0;
   int last_t = -1;
   double last_rho = -1.0;
+  double need = -1.0;  // predicted iterations to `tol` at the last check (-1: no prediction)
+  std::vector<std::pair<int, double>> hist;  // (t, rho) of the earlier checks of this phase
   int plan(int t, double rho, double tol) {
+    need = -1.0;
     if (every > 0) return next = t + every;
+    // decay rate against the latest check at least kRateSpan iterations back
+    // where there is one (the maximum over the triplets moves unevenly from
+    // one iteration to the next), else against the last check
+    int bt = last_t;
+    double br = last_rho;
+    for (auto it = hist.rbegin(); it != hist.rend(); ++it)
+      if (it->first <= t - kRateSpan) {
+        bt = it->first;
+        br = it->second;
+        break;
+      }
     int gap = 4;   // after the first check: the early decay is not yet geometric
-    if (last_t >= 0 && rho > 0.0 && last_rho > rho) {
-      const double rate = std::pow(rho / last_rho, 1.0 / (t - last_t));
-      const double need = std::log(tol / rho) / std::log(rate);
+    if (bt >= 0 && rho > 0.0 && br > rho) {
+      const double rate = std::pow(rho / br, 1.0 / (t - bt));
+      need = std::log(tol / rho) / std::log(rate);
       gap = static_cast<int>(0.9 * need);
     } else if (last_t >= 0) {
       gap = 2 * (t - last_t);
     }
     gap = gap < 1 ? 1 : (gap > kMaxCheckGap ? kMaxCheckGap : gap);
+    hist.emplace_back(t, rho);
     last_t = t;
     last_rho = rho;
     return next = t + gap;
   }
 };
 
+// Runs iterations in storage type T from the current Qc.  Returns 1 when the
+// Ritz triplets held in st satisfy the stopping rule of this phase (tolerance
+// `tol`, or the fixed count), 0 when max_iter was reached.
 // stall_rate > 0: also stop (returning 2) when rho has fallen by less than a
 // factor stall_rate per iteration since the previous check -- the precision
-// floor of the block storage has been reached.
+// floor of the block storage has been reached.  phase_cap > 0: stop (2) after
+// that iteration.  probe: stop (3) at the first check that predicts the
+// iterations still needed (st.probe_need).
 template <typename T>
 int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, double tol, bool fixed, int t0,
-              hipStream_t stream, double stall_rate = 0.0, int phase_cap = 0) {
+              hipStream_t stream, double stall_rate = 0.0, int phase_cap = 0, bool probe = false) {
   const int l = st.l;
   CheckSchedule sched;
   sched.every = prm->check_every > 0 ? prm->check_every : 0;
@@ -287,6 +347,7 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
     st.applies++;
     if (!fixed && st.have_ritz && st.ritz_iter == t - 1) {
       st.residual = residual<T>(st, Y, stream);
+      trace_check(st, std::is_same<T, bf16>::value ? "bf16" : (std::is_same<T, float>::value ? "fp32" : "fp64"), t - 1);
       if (st.residual <= tol) {
         st.iterations = t - 1;
         return 1;
@@ -301,6 +362,12 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
         return 2;
       }
       sched.plan(t - 1, st.residual, tol);
+      // probe: stop (returning 3) once the decay rate predicts the rest
+      if (probe && sched.need > 0.0) {
+        st.iterations = t - 1;
+        st.probe_need = static_cast<int>(std::ceil(sched.need));
+        return 3;
+      }
     }
     if (!fixed && phase_cap > 0 && t >= phase_cap && st.have_ritz && st.ritz_iter == t - 1) {
       st.iterations = t - 1;
@@ -342,6 +409,27 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
   }
 }
 
+// Blocks of st from storage S to storage D: Qc converted, the other blocks
+// reallocated; the Ritz state of the old storage is dropped.
+template <typename D, typename S>
+void switch_storage(SvdState& st, hipStream_t stream) {
+  DevBuf qcn;
+  qcn.ensure(static_cast<size_t>(st.c) * st.ld * sizeof(D));
+  launch_convert<D, S>(st.c, st.l, st.qc.as<S>(), st.ld, qcn.as<D>(), st.ld, stream);
+  ISVD_HIP(hipStreamSynchronize(stream));
+  st.qc.release();
+  st.w.release();
+  st.qr.release();
+  st.y.release();
+  std::swap(st.qc.p, qcn.p);
+  std::swap(st.qc.bytes, qcn.bytes);
+  st.w.ensure(static_cast<size_t>(st.c) * st.ld * sizeof(D));
+  st.qr.ensure(static_cast<size_t>(st.r) * st.ld * sizeof(D));
+  st.y.ensure(static_cast<size_t>(st.r) * st.ld * sizeof(D));
+  st.have_ritz = false;
+  st.ritz_iter = -1;
+}
+
 template <typename T>
 void load_start_block(SvdState& st, const isvd_svd_params* prm, hipStream_t stream) {
   if (prm->omega) {
@@ -373,34 +461,54 @@ isvd_status svd_bf16(isvd_operator* op, const isvd_svd_params* prm, void* U, int
     finalize<bf16, float>(st, op, U, ldu, S, V, ldv, stream);
     return ok ? ISVD_OK : ISVD_E_NOT_CONVERGED;
   }
-  // BF16 until rho <= fp32_switch_tol, then widen Qc and continue in FP32.
-  const int ok16 = run_phase<bf16>(st, op, prm, prm->fp32_switch_tol, false, 0, stream,
-                                  prm->bf16_max_iter > 0 ? 0.0 : 0.98, prm->bf16_max_iter);
+  // BF16 until rho <= fp32_switch_tol or the residual stalls (or for
+  // bf16_max_iter iterations), then FP32.
+  const bool auto_len = prm->bf16_max_iter <= 0;
+  const int ok16 = run_phase<bf16>(st, op, prm, prm->fp32_switch_tol, false, 0, stream, auto_len ? 0.98 : 0.0,
+                                  prm->bf16_max_iter);
   if (!ok16) {
     st.bf16_iterations = st.iterations + 1;
     finalize<bf16, float>(st, op, U, ldu, S, V, ldv, stream);
     return ISVD_E_NOT_CONVERGED;
   }
-  const int t_switch = st.iterations + 1;
-  st.bf16_iterations = t_switch;
-  // The BF16 phase stopped with Qc of iteration t_switch - 1 and one extra product;
-  // restart the FP32 phase from that Qc.
-  DevBuf qc32;
-  qc32.ensure(static_cast<size_t>(st.c) * st.ld * sizeof(float));
-  launch_convert<float, bf16>(st.c, st.l, st.qc.as<bf16>(), st.ld, qc32.as<float>(), st.ld, stream);
-  ISVD_HIP(hipStreamSynchronize(stream));
-  st.qc.release();
-  st.w.release();
-  st.qr.release();
-  st.y.release();
-  std::swap(st.qc.p, qc32.p);
-  std::swap(st.qc.bytes, qc32.bytes);
-  st.w.ensure(static_cast<size_t>(st.c) * st.ld * sizeof(float));
-  st.qr.ensure(static_cast<size_t>(st.r) * st.ld * sizeof(float));
-  st.y.ensure(static_cast<size_t>(st.r) * st.ld * sizeof(float));
-  st.have_ritz = false;
-  st.ritz_iter = -1;
-  const int ok = run_phase<float>(st, op, prm, prm->tol, false, t_switch, stream);
+  // The BF16 phase stopped with Qc of iteration t - 1 and one extra product;
+  // the next phase restarts from that Qc.
+  int t = st.iterations + 1;
+  int bf16_its = t;
+  switch_storage<float, bf16>(st, stream);
+  // With the automatic switch, the residual seen in BF16 may be the floor of
+  // the BF16 rounding of the blocks (amplified by the largest singular value)
+  // while the subspace itself still converges as fast as in FP32.  A short
+  // FP32 probe measures the true residual and its decay; while the predicted
+  // rest exceeds the FP32 iterations needed after a BF16 stretch (kPolish) by
+  // at least kMinBack, the blocks go back to BF16 for the difference (at most
+  // as many iterations as done so far), then the probe repeats.  The early
+  // FP32 decay is a little faster than the later one, so the prediction is
+  // taken 10% longer.
+  constexpr int kPolish = 10, kMinBack = 8, kMaxRounds = 3;
+  constexpr double kNeedMargin = 1.1;
+  for (int round = 0; auto_len && round < kMaxRounds; ++round) {
+    const int pr = run_phase<float>(st, op, prm, prm->tol, false, t, stream, 0.0, 0, true);
+    if (pr != 3) {
+      st.bf16_iterations = bf16_its;
+      finalize<float, float>(st, op, U, ldu, S, V, ldv, stream);
+      return pr == 1 ? ISVD_OK : ISVD_E_NOT_CONVERGED;
+    }
+    t = st.iterations + 1;
+    int back = static_cast<int>(std::ceil(kNeedMargin * st.probe_need)) - kPolish;
+    back = std::min(back, std::max(16, t));
+    back = std::min(back, prm->max_iter - 1 - t - kPolish);
+    if (back < kMinBack) break;
+    switch_storage<bf16, float>(st, stream);
+    isvd_svd_params fixed_prm = *prm;
+    fixed_prm.q = t + back - 1;   // iterations t .. t + back - 1, no residual checks
+    run_phase<bf16>(st, op, &fixed_prm, 0.0, true, t, stream);
+    bf16_its += back;
+    t = st.iterations + 1;
+    switch_storage<float, bf16>(st, stream);
+  }
+  st.bf16_iterations = bf16_its;
+  const int ok = run_phase<float>(st, op, prm, prm->tol, false, t, stream);
   finalize<float, float>(st, op, U, ldu, S, V, ldv, stream);
   return ok ? ISVD_OK : ISVD_E_NOT_CONVERGED;
 }

@@ -237,8 +237,9 @@ isvd_status isvd_small_svd(int64_t n, const double* A, double* Uo, double* s, do
  * ------------------------------------------------------------------------ */
 
 /* on != 0: from now on every sparse pass is bracketed by a hipEvent pair on
- * its launch stream (adds one host sync per pass to read the CSR size); the
- * record is cleared.  on == 0 stops recording. */
+ * its launch stream (two event records per pass, no host synchronisation; the
+ * byte counts come from the host copy of the CSR sizes); the record is
+ * cleared.  on == 0 stops recording. */
 isvd_status isvd_profile_spmm_enable(int on);
 
 /* Totals over the passes recorded since the last enable/read (host outputs):

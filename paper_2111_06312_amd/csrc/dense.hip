@@ -189,7 +189,7 @@ constexpr int gram_rows_per_wave() {
   return kGramPF / words > 0 ? kGramPF / words : 1;
 }
 
-template <typename TA, typename TB, int CS, int VW, bool SAME>
+template <typename TA, typename TB, int CS, int VW, bool SAME, int KSPLIT>
 __global__ __launch_bounds__(64 * kGramMaxWaves) void gram_partial_kernel(
     int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb, int tm, int tp, int nbi,
     int nbj, int njobs, int64_t rows_per_block, int rb, int ldsa, int ldsb, double* partial, int mp, int pp) {
@@ -202,7 +202,9 @@ __global__ __launch_bounds__(64 * kGramMaxWaves) void gram_partial_kernel(
   const int li = lane & 15, lk = lane >> 4;
   const int nw = static_cast<int>(blockDim.x >> 6);
   const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-  const int job = static_cast<int>(blockIdx.y) * nw + wv;
+  // KSPLIT == 2: waves wv and wv + nj share job wv, each taking half the k-steps
+  const int nj = nw / KSPLIT, set = KSPLIT == 1 ? 0 : wv / nj;
+  const int job = static_cast<int>(blockIdx.y) * nj + (wv - set * nj);
   const bool has_job = job < njobs;
   // job -> block (bi, bj): upper triangle row by row for A^T A, else row-major
   int bi = 0, bj = 0;
@@ -292,10 +294,37 @@ __global__ __launch_bounds__(64 * kGramMaxWaves) void gram_partial_kernel(
     const S* As = buf0 + cur * per_buf;
     const S* Bs = SAME ? As : As + rb * ldsa;
     const int ldb_s = SAME ? ldsa : ldsb;
-    if (has_job) gram_ksteps(As, Bs, ldsa, ldb_s, rb / 4, ti0, tj0, li, lk, diag, acc);
+    const int nks = rb / (4 * KSPLIT);   // k-steps of this wave in the chunk
+    if (has_job)
+      gram_ksteps(As + set * nks * 4 * ldsa, Bs + set * nks * 4 * ldb_s, ldsa, ldb_s, nks, ti0, tj0, li, lk, diag,
+                  acc);
     if (more) stage(buf0 + (cur ^ 1) * per_buf);
     __syncthreads();
     cur ^= 1;
+  }
+  if constexpr (KSPLIT == 2) {
+    // the staging buffers are free (the chunk loop ends with a barrier)
+    double* xch = reinterpret_cast<double*>(gram_smem) + static_cast<int64_t>(wv - set * nj) * kGramRB * kGramRB * 4 * 64;
+    if (set == 1 && has_job) {
+#pragma unroll
+      for (int r = 0; r < kGramRB; ++r)
+#pragma unroll
+        for (int c = 0; c < kGramRB; ++c)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) xch[((r * kGramRB + c) * 4 + q) * 64 + lane] = acc[r][c][q];
+    }
+    __syncthreads();
+    if (set == 1) return;
+    if (has_job) {
+#pragma unroll
+      for (int r = 0; r < kGramRB; ++r)
+#pragma unroll
+        for (int c = 0; c < kGramRB; ++c) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[r][c][q] += xch[((r * kGramRB + c) * 4 + q) * 64 + lane];
+          __builtin_amdgcn_sched_barrier(0);  // one tile's loads at a time (register budget)
+        }
+    }
   }
   if (!has_job) return;
   double* part = partial + static_cast<int64_t>(blockIdx.x) * mp * pp;
@@ -338,15 +367,16 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int npar
 }
 
 struct GramPlan {
-  int mp, pp, tm, tp, nbi, nbj, njobs, waves, groups, vw, cs, rb, ldsa, ldsb, nparts;
+  int mp, pp, tm, tp, nbi, nbj, njobs, waves, groups, vw, cs, rb, ldsa, ldsb, nparts, ksplit;
   int64_t rows_per_block;
   size_t lds;
 };
 
-// Row slices: at most kGramMaxParts, each a multiple of 64 rows.
+// Row slices: at most kGramMaxParts (one per CU), each a multiple of 16 rows
+// (at least 64), so that large blocks use every CU.
 int64_t gram_rows_per_part(int64_t rows) {
   const int64_t want = ceil_div(rows > 0 ? rows : 1, kGramMaxParts);
-  return round_up(want < 64 ? 64 : want, 64);
+  return round_up(want < 64 ? 64 : want, 16);
 }
 
 constexpr int kGramCS2[] = {1, 2, 3, 4, 5, 6, 8, 16};   // paired-column loads
@@ -381,17 +411,28 @@ GramPlan plan_gram(int64_t rows, int m, int p, bool same, int esize, bool paired
       }
   }
   ISVD_CHECK(g.cs > 0, ISVD_E_INVALID, "gram: more than 2048 columns");
+  // One wave per job leaves the four SIMDs of a CU unevenly loaded when the
+  // job count is not a multiple of four (A^T A with l = 144: six jobs, two
+  // SIMDs with two jobs each); then two waves share each job, taking the two
+  // halves of every chunk's k-steps, and their sums meet in LDS at the end.
+  g.ksplit = (same && g.cs <= 4 && g.groups == 1 && g.njobs % 4 != 0 && 2 * g.njobs <= kGramMaxWaves) ? 2 : 1;
+  g.waves *= g.ksplit;
   const int words = g.cs * g.vw * esize / 4 * (same ? 1 : 2);
   const int J = kGramPF / words > 0 ? kGramPF / words : 1;
   if (g.waves * J < 4) g.waves = static_cast<int>(ceil_div(4, J));   // at least one k-step per chunk
   g.ldsa = gram_lds_ld(mpa, esize);
   g.ldsb = same ? 0 : gram_lds_ld(ppa, esize);
-  g.rb = (g.waves * J) / 4 * 4;
+  const int rstep = 4 * g.ksplit;   // whole k-steps for every wave sharing a job
+  if (g.waves * J < rstep) g.waves = static_cast<int>(ceil_div(rstep, J));
+  g.rb = (g.waves * J) / rstep * rstep;
   if (g.rb > 64) g.rb = 64;
-  while (g.rb > 4 && static_cast<size_t>(2) * g.rb * (g.ldsa + g.ldsb) * esize > kGramMaxLds) g.rb -= 4;
+  while (g.rb > rstep && static_cast<size_t>(2) * g.rb * (g.ldsa + g.ldsb) * esize > kGramMaxLds) g.rb -= rstep;
   ISVD_CHECK(static_cast<size_t>(2) * g.rb * (g.ldsa + g.ldsb) * esize <= kGramMaxLds, ISVD_E_INVALID,
              "gram: block too wide");
   g.lds = static_cast<size_t>(2) * g.rb * (g.ldsa + g.ldsb) * esize;
+  // the second wave of each shared job hands its accumulators over in LDS
+  if (g.ksplit == 2)
+    g.lds = std::max(g.lds, static_cast<size_t>(g.waves / 2) * kGramRB * kGramRB * 4 * 64 * sizeof(double));
   g.rows_per_block = gram_rows_per_part(rows);
   g.nparts = static_cast<int>(ceil_div(rows > 0 ? rows : 1, g.rows_per_block));
   return g;
@@ -400,7 +441,18 @@ GramPlan plan_gram(int64_t rows, int m, int p, bool same, int esize, bool paired
 template <typename TA, typename TB, int CS, int VW, bool SAME>
 void gram_launch(const GramPlan& g, int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
                  double* work, hipStream_t stream) {
-  hipLaunchKernelGGL((gram_partial_kernel<TA, TB, CS, VW, SAME>), dim3(g.nparts, g.groups), dim3(64 * g.waves),
+  // two waves per job only for small A^T A (at most three 3 x 3 blocks a side)
+  if constexpr (SAME && CS <= 4) {
+    if (g.ksplit == 2) {
+      hipLaunchKernelGGL((gram_partial_kernel<TA, TB, CS, VW, SAME, 2>), dim3(g.nparts, g.groups), dim3(64 * g.waves),
+                         g.lds, stream, rows, m, p, A, lda, B, ldb, g.tm, g.tp, g.nbi, g.nbj, g.njobs,
+                         g.rows_per_block, g.rb, g.ldsa, g.ldsb, work, g.mp, g.pp);
+      ISVD_LAUNCH_CHECK();
+      return;
+    }
+  }
+  ISVD_CHECK(g.ksplit == 1, ISVD_E_INVALID, "gram: split jobs need a small A^T A");
+  hipLaunchKernelGGL((gram_partial_kernel<TA, TB, CS, VW, SAME, 1>), dim3(g.nparts, g.groups), dim3(64 * g.waves),
                      g.lds, stream, rows, m, p, A, lda, B, ldb, g.tm, g.tp, g.nbi, g.nbj, g.njobs, g.rows_per_block,
                      g.rb, g.ldsa, g.ldsb, work, g.mp, g.pp);
   ISVD_LAUNCH_CHECK();

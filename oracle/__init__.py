@@ -17,6 +17,9 @@ checked against the paper by eye:
 - isvd.py       : Algorithm 1 (randomized SVD of an implicit matrix) with
                   Householder QR or Cholesky orthonormalisation
                   (Algorithm 2), and the per-triplet residual.
+- learners.py   : the closed-form learners on the SVD: node embeddings and
+                  pair scores (Eq. 5) and the least-norm model
+                  W* = V S^+ U^T Y (Eq. 7, Theorem 1).
 - mlp.py        : the warm-start network, its subspace loss and a
                   hand-derived backward pass.
 - philox.py     : the Philox4x32-10 counter-based generator and the

@@ -51,7 +51,95 @@ def parse():
                     help="trained warm-start parameters (.npy); each step then computes the features, the "
                          "network's start block and the iSVD from it, and the same steps with a Gaussian "
                          "start block are timed for comparison")
+    ap.add_argument("--learners", action="store_true",
+                    help="time the closed-form learners instead: Eq. 5 embeddings and pair scores on the "
+                         "rank-128 SVD of the n = 200,000 NE workload, and the Eq. 7 least-norm model on the "
+                         "rank-64 SVD of the n = 170,000 feature-propagation workload (one JSON line)")
+    ap.add_argument("--pairs", type=int, default=2_000_000)
+    ap.add_argument("--label-frac", type=float, default=0.5)
     return ap.parse_args()
+
+
+def _timed(torch, fn, reps):
+    """Mean HIP-event duration (s) of fn() on the current stream over reps calls."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    out = None
+    for a, b in ev:
+        a.record()
+        out = fn()
+        b.record()
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / reps / 1e3, out
+
+
+def learners_bench(args, lib, torch, np):
+    """Closed-form learners (Section 3) on resident SVD outputs.
+
+    NE (Eq. 5): U, S, V of the n = 200,000 Chung-Lu NE matrix (k = 128,
+    FP32); embeddings L, R and `--pairs` uniform random pair scores.  NC
+    (Eq. 7): U, S, V of the n = 170,000 SBM feature-propagation matrix
+    (d = 128, L = 3, k = 64, FP32), labels = the 40 planted blocks one-hot,
+    `--label-frac` of the rows labelled (option (i)).  Algorithmic bytes:
+    embeddings read and write U and V once; a score gathers one row of U
+    and of V (+ two int64 indices, one FP64 score); the model reads the
+    labelled rows of U and Y once, V once and writes W."""
+    from synth import CONFIGS, block_features
+    from synth.configs import make_graph
+
+    out = {}
+    c2 = CONFIGS["c2"]
+    g = make_graph(c2)
+    op = lib.Operator(g, form="ne", coeffs=c2.coeffs, lam=c2.lam, self_loops=c2.self_loops, precision=lib.FP32)
+    U, S, V, info = op.truncated_svd(c2.k, c2.p, tol=1e-4, max_iter=2000, seed=0)
+    op.close()
+    n, k = U.shape
+    es = 4
+    rng = np.random.default_rng(5)
+    pi = torch.as_tensor(rng.integers(0, n, args.pairs)).cuda()
+    pj = torch.as_tensor(rng.integers(0, n, args.pairs)).cuda()
+    for _ in range(args.warmup):
+        lib.ne_embeddings(U, S, V)
+        lib.ne_scores(U, S, V, pi, pj)
+    t_emb, _ = _timed(torch, lambda: lib.ne_embeddings(U, S, V), args.steps)
+    t_sc, _ = _timed(torch, lambda: lib.ne_scores(U, S, V, pi, pj), args.steps)
+    b_emb = 2 * 2 * n * k * es
+    b_sc = args.pairs * (2 * k * es + 16 + 8)
+    out["ne_embeddings"] = {"workload": c2.name, "rows": [n, n], "k": k, "s": round(t_emb, 6),
+                            "bytes": b_emb, "gbps": round(b_emb / t_emb / 1e9, 1)}
+    out["ne_scores"] = {"workload": c2.name, "pairs": args.pairs, "k": k, "s": round(t_sc, 6),
+                        "bytes": b_sc, "gbps": round(b_sc / t_sc / 1e9, 1),
+                        "pairs_per_s": round(args.pairs / t_sc)}
+    del U, V, pi, pj
+    c3 = CONFIGS["c3"]
+    g = make_graph(c3)
+    x = block_features(g.blocks, c3.d, seed=1000 + c3.index)
+    op = lib.Operator(g, form="featprop", X=torch.as_tensor(x).cuda(), L=c3.L, precision=lib.FP32)
+    U, S, V, info = op.truncated_svd(c3.k, c3.p, tol=1e-4, max_iter=2000, seed=0)
+    op.close()
+    ny = int(g.blocks.max()) + 1
+    y = np.zeros((g.n, ny), dtype=np.float32)
+    y[np.arange(g.n), g.blocks] = 1.0
+    Y = torch.as_tensor(y).cuda()
+    nl = int(args.label_frac * g.n)
+    rows = torch.as_tensor(np.sort(np.random.default_rng(6).choice(g.n, nl, replace=False))).cuda()
+    for _ in range(args.warmup):
+        lib.nc_fit(U, S, V, Y, rows=rows)
+    t_nc, _ = _timed(torch, lambda: lib.nc_fit(U, S, V, Y, rows=rows), args.steps)
+    kk, d = U.shape[1], V.shape[0]
+    b_nc = nl * (kk + ny) * es + nl * 8 + d * kk * es + d * ny * 8
+    out["nc_fit"] = {"workload": c3.name, "labelled_rows": nl, "k": kk, "classes": ny, "d": d,
+                     "s": round(t_nc, 6), "bytes": b_nc, "gbps": round(b_nc / t_nc / 1e9, 1)}
+    dom = max(out, key=lambda key: out[key]["s"])
+    line = {
+        "metric": "closed-form learner time on resident SVD outputs (Eq. 5 and Eq. 7)",
+        "value": round(sum(v["s"] for v in out.values()), 6), "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "vs_baseline": None,
+        "dtype": "f32 in, f64 sums", "data": "synthetic",
+        "config": {"workload": "learners_" + c2.name + "+" + c3.name, **out},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": out[dom]["gbps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(out[dom]["gbps"] / HBM_PEAK_GBPS, 4), "traffic": None},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def cpu_baseline(g, cfg, applies, orths):
@@ -108,6 +196,9 @@ def main():
         torch.cuda.synchronize()
         print("[bench] calibration copies: 3 x 1 GiB device-to-device", file=sys.stderr, flush=True)
         del src, dst
+    if args.learners:
+        learners_bench(args, lib, torch, np)
+        return
     cfg = CONFIGS[args.config]
     prec_name = args.precision or ("bf16" if cfg.precision == "bf16" else "fp32")
     precision = lib.BF16 if prec_name == "bf16" else lib.FP32

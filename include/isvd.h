@@ -233,6 +233,41 @@ isvd_status isvd_small_svd(int64_t n, const double* A, double* Uo, double* s, do
                            void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Closed-form learners on a rank-k SVD (Section 3).  U (rows_u x k), V
+ * (rows_v x k) and S (k, FP64) are the outputs of isvd_truncated_svd;
+ * precision ISVD_FP64 (double U, V, Y) or ISVD_FP32 (float; BF16 operators
+ * also return float U, V).  All pointers device, row-major.  Index arrays
+ * are int64 and checked on the device: an index outside its range makes
+ * the call return ISVD_E_INVALID (the outputs it touched are undefined).
+ * These calls synchronise the stream before returning.
+ * ------------------------------------------------------------------------ */
+
+/* Node embeddings of Eq. 5: L = U S^(1/2) (rows_u x k, ldl), R = V S^(1/2)
+ * (rows_v x k, ldr), in the precision of U and V.  L or R may be NULL. */
+isvd_status isvd_ne_embeddings(int64_t rows_u, int64_t rows_v, int64_t k, isvd_precision precision,
+                               const void* U, int64_t ldu, const double* S, const void* V, int64_t ldv,
+                               void* L, int64_t ldl, void* R, int64_t ldr, void* stream);
+
+/* Pair scores of Eq. 5: scores[p] = <L_i, R_j> = sum_t U[i][t] S[t] V[j][t]
+ * with i = pi[p], j = pj[p] (FP64 products and sums; npairs doubles). */
+isvd_status isvd_ne_scores(int64_t k, isvd_precision precision, const void* U, int64_t ldu, int64_t rows_u,
+                           const double* S, const void* V, int64_t ldv, int64_t rows_v, int64_t npairs,
+                           const int64_t* pi, const int64_t* pj, double* scores, void* stream);
+
+/* Least-norm linear model of Eq. 7 (Theorem 1): W = V S^+ U^T Y, multiplied
+ * right to left: U^T Y (FP64 sums of exact products, k + ny <= 2048), then
+ * S^+ (1/s_t for s_t > rcond * max(S), else 0; rcond = 0 is the literal
+ * rule), then V.  Y: rows_u x ny, the element type of U.  nsub >= 0:
+ * row_subset holds nsub indices into [0, rows_u) (repeats allowed; NULL if
+ * nsub = 0) and only those rows of U and Y are used (the labelled nodes,
+ * Section 3.2 option (i)); nsub = -1: all rows, row_subset ignored.
+ * W: rows_v x ny FP64 (zero when nsub = 0). */
+isvd_status isvd_nc_fit(int64_t rows_u, int64_t rows_v, int64_t k, int64_t ny, isvd_precision precision,
+                        const void* U, int64_t ldu, const double* S, const void* V, int64_t ldv, const void* Y,
+                        int64_t ldy, const int64_t* row_subset, int64_t nsub, double rcond, double* W,
+                        int64_t ldw, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Measurement of the sparse passes (the kernel that bounds every product).
  * ------------------------------------------------------------------------ */
 

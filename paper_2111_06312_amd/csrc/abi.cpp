@@ -1,6 +1,8 @@
 // extern "C" entry points: argument checks, exception barrier, last-error text.
+#include <algorithm>
 #include <string>
 
+#include "learners.h"
 #include "operator.h"
 
 namespace isvd {
@@ -193,6 +195,114 @@ isvd_status isvd_small_svd(int64_t n, const double* A, double* Uo, double* s, do
     work.ensure(jacobi_workspace_doubles(static_cast<int>(n)) * sizeof(double));
     launch_jacobi_svd(static_cast<int>(n), A, n, Uo, s, Vo, work.as<double>(), nullptr, st);
     ISVD_HIP(hipStreamSynchronize(st));
+    return ISVD_OK;
+  });
+}
+
+namespace {
+// Elements of U/V/Y for a learner call: FP64 or FP32 only.
+size_t learner_esize(isvd_precision p) {
+  ISVD_CHECK(p == ISVD_FP64 || p == ISVD_FP32, ISVD_E_INVALID,
+             "learners take FP64 or FP32 factors (BF16 operators return FP32 U and V)");
+  return p == ISVD_FP64 ? 8 : 4;
+}
+// Waits for the stream and turns the device index flag into an error.
+void check_index_flag(const DevBuf& bad, hipStream_t s) {
+  int flag = 0;
+  ISVD_HIP(hipMemcpyAsync(&flag, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  ISVD_HIP(hipStreamSynchronize(s));
+  ISVD_CHECK(flag == 0, ISVD_E_INVALID, "index out of range");
+}
+}  // namespace
+
+isvd_status isvd_ne_embeddings(int64_t rows_u, int64_t rows_v, int64_t k, isvd_precision precision, const void* U,
+                               int64_t ldu, const double* S, const void* V, int64_t ldv, void* L, int64_t ldl,
+                               void* R, int64_t ldr, void* stream) {
+  return guarded([&]() -> isvd_status {
+    learner_esize(precision);
+    ISVD_CHECK(S && k >= 1 && rows_u >= 0 && rows_v >= 0, ISVD_E_INVALID, "bad embedding arguments");
+    ISVD_CHECK(!L || (U && ldu >= k && ldl >= k), ISVD_E_INVALID, "bad L/U arguments");
+    ISVD_CHECK(!R || (V && ldv >= k && ldr >= k), ISVD_E_INVALID, "bad R/V arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int kk = static_cast<int>(k);
+    if (precision == ISVD_FP64) {
+      if (L) launch_ne_embed<double>(rows_u, kk, static_cast<const double*>(U), ldu, S, static_cast<double*>(L), ldl, s);
+      if (R) launch_ne_embed<double>(rows_v, kk, static_cast<const double*>(V), ldv, S, static_cast<double*>(R), ldr, s);
+    } else {
+      if (L) launch_ne_embed<float>(rows_u, kk, static_cast<const float*>(U), ldu, S, static_cast<float*>(L), ldl, s);
+      if (R) launch_ne_embed<float>(rows_v, kk, static_cast<const float*>(V), ldv, S, static_cast<float*>(R), ldr, s);
+    }
+    ISVD_HIP(hipStreamSynchronize(s));
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_ne_scores(int64_t k, isvd_precision precision, const void* U, int64_t ldu, int64_t rows_u,
+                           const double* S, const void* V, int64_t ldv, int64_t rows_v, int64_t npairs,
+                           const int64_t* pi, const int64_t* pj, double* scores, void* stream) {
+  return guarded([&]() -> isvd_status {
+    learner_esize(precision);
+    ISVD_CHECK(U && V && S && k >= 1 && ldu >= k && ldv >= k && npairs >= 0 && (npairs == 0 || (pi && pj && scores)),
+               ISVD_E_INVALID, "bad score arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf bad;
+    bad.ensure(sizeof(int));
+    ISVD_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+    if (precision == ISVD_FP64)
+      launch_pair_scores<double>(static_cast<int>(k), static_cast<const double*>(U), ldu, rows_u, S,
+                                 static_cast<const double*>(V), ldv, rows_v, npairs, pi, pj, scores, bad.as<int>(), s);
+    else
+      launch_pair_scores<float>(static_cast<int>(k), static_cast<const float*>(U), ldu, rows_u, S,
+                                static_cast<const float*>(V), ldv, rows_v, npairs, pi, pj, scores, bad.as<int>(), s);
+    check_index_flag(bad, s);
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_nc_fit(int64_t rows_u, int64_t rows_v, int64_t k, int64_t ny, isvd_precision precision,
+                        const void* U, int64_t ldu, const double* S, const void* V, int64_t ldv, const void* Y,
+                        int64_t ldy, const int64_t* row_subset, int64_t nsub, double rcond, double* W,
+                        int64_t ldw, void* stream) {
+  return guarded([&]() -> isvd_status {
+    const size_t es = learner_esize(precision);
+    ISVD_CHECK(U && V && S && Y && W && k >= 1 && k <= 1024 && ny >= 1 && k + ny <= 2048 && rows_u >= 0 &&
+                   rows_v >= 0 && ldu >= k && ldv >= k && ldy >= ny && ldw >= ny && rcond >= 0.0,
+               ISVD_E_INVALID, "bad nc fit arguments (k <= 1024, k + ny <= 2048)");
+    ISVD_CHECK(nsub == -1 || (nsub >= 0 && (row_subset || nsub == 0)), ISVD_E_INVALID, "bad row subset");
+    const bool subset = nsub >= 0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int kk = static_cast<int>(k), yy = static_cast<int>(ny);
+    DevBuf bad, ug, yg, tm, work;
+    bad.ensure(sizeof(int));
+    ISVD_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+    const int64_t n = subset ? nsub : rows_u;
+    tm.ensure(static_cast<size_t>(k) * ny * sizeof(double));
+    work.ensure(gram_workspace_doubles(n, kk, yy) * sizeof(double));
+    auto fit = [&](auto tag) {
+      using T = decltype(tag);
+      const T* u = static_cast<const T*>(U);
+      const T* y = static_cast<const T*>(Y);
+      int64_t lu = ldu, ly = ldy;
+      if (subset && nsub > 0) {
+        ug.ensure(static_cast<size_t>(std::max<int64_t>(nsub, 1)) * k * es);
+        yg.ensure(static_cast<size_t>(std::max<int64_t>(nsub, 1)) * ny * es);
+        launch_gather_rows<T>(nsub, k, row_subset, rows_u, u, ldu, ug.as<T>(), k, bad.as<int>(), s);
+        launch_gather_rows<T>(nsub, ny, row_subset, rows_u, y, ldy, yg.as<T>(), ny, bad.as<int>(), s);
+        u = ug.as<T>();
+        y = yg.as<T>();
+        lu = k;
+        ly = ny;
+      }
+      if (n == 0) {  // no labelled rows: U^T Y and W are zero
+        if (rows_v > 0) ISVD_HIP(hipMemset2DAsync(W, ldw * sizeof(double), 0, ny * sizeof(double), rows_v, s));
+        return;
+      }
+      launch_gram<T>(n, kk, yy, u, lu, y, ly, false, tm.as<double>(), ny, work.as<double>(), s);
+      launch_nc_apply<T>(rows_v, kk, yy, static_cast<const T*>(V), ldv, S, rcond, tm.as<double>(), ny, W, ldw, s);
+    };
+    if (precision == ISVD_FP64) fit(double{});
+    else fit(float{});
+    check_index_flag(bad, s);
     return ISVD_OK;
   });
 }

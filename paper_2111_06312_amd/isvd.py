@@ -103,6 +103,10 @@ def load():
     lib.isvd_ws_forward.argtypes = [vp, i64, vp, vp, i64, vp]
     lib.isvd_ws_train_step.argtypes = [vp, i64, vp, vp, i64, ct.c_double, ct.POINTER(ct.c_double), vp, vp]
     lib.isvd_ws_omega.argtypes = [vp, vp, vp, st, ct.c_uint64, vp, i64, ct.POINTER(st), vp]
+    lib.isvd_ne_embeddings.argtypes = [i64, i64, i64, st, vp, i64, vp, vp, i64, vp, i64, vp, i64, vp]
+    lib.isvd_ne_scores.argtypes = [i64, st, vp, i64, i64, vp, vp, i64, i64, i64, vp, vp, vp, vp]
+    lib.isvd_nc_fit.argtypes = [i64, i64, i64, i64, st, vp, i64, vp, vp, i64, vp, i64, vp, i64, ct.c_double,
+                                vp, i64, vp]
     lib.isvd_profile_spmm_enable.argtypes = [st]
     lib.isvd_profile_spmm_read.argtypes = [ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
                                            ct.POINTER(ct.c_double), ct.POINTER(i64)]
@@ -262,6 +266,56 @@ def small_svd(A):
     s = torch.empty(n, dtype=torch.float64, device=A.device)
     _check(_lib.isvd_small_svd(n, _ptr(A), _ptr(U), _ptr(s), _ptr(V), _stream()))
     return U, s, V
+
+
+def _factor_prec(U, S, V):
+    assert U.dtype == V.dtype and U.dtype in (torch.float32, torch.float64), "U and V must be FP32 or FP64"
+    assert U.shape[1] == V.shape[1], "U and V need the same rank"
+    assert S.dtype == torch.float64 and S.is_contiguous() and S.shape[0] == U.shape[1], "S: k FP64 values"
+    return _PREC[U.dtype]
+
+
+def ne_embeddings(U, S, V):
+    """(L, R) = (U S^(1/2), V S^(1/2)) of Eq. 5, in the precision of U and V."""
+    load()
+    prec = _factor_prec(U, S, V)
+    k = U.shape[1]
+    L = torch.empty_like(U, memory_format=torch.contiguous_format)
+    R = torch.empty_like(V, memory_format=torch.contiguous_format)
+    _check(_lib.isvd_ne_embeddings(U.shape[0], V.shape[0], k, prec, _ptr(U), _ld(U), _ptr(S), _ptr(V), _ld(V),
+                                   _ptr(L), k, _ptr(R), k, _stream()))
+    return L, R
+
+
+def ne_scores(U, S, V, pi, pj):
+    """FP64 scores U[i] S V[j]^T (Eq. 5) of the pairs (pi[p], pj[p]) (int64 device tensors)."""
+    load()
+    prec = _factor_prec(U, S, V)
+    pi = pi.to(torch.int64).contiguous()
+    pj = pj.to(torch.int64).contiguous()
+    assert pi.shape == pj.shape and pi.dim() == 1
+    out = torch.empty(pi.shape[0], dtype=torch.float64, device=U.device)
+    _check(_lib.isvd_ne_scores(U.shape[1], prec, _ptr(U), _ld(U), U.shape[0], _ptr(S), _ptr(V), _ld(V), V.shape[0],
+                               pi.shape[0], _ptr(pi), _ptr(pj), _ptr(out), _stream()))
+    return out
+
+
+def nc_fit(U, S, V, Y, rows=None, rcond=0.0):
+    """Least-norm W = V S^+ U^T Y of Eq. 7 (FP64, V.shape[0] x Y.shape[1]).
+
+    Y has the dtype of U; rows (int64 device tensor) keeps only those rows of
+    U and Y (the labelled nodes)."""
+    load()
+    prec = _factor_prec(U, S, V)
+    assert Y.dtype == U.dtype and Y.shape[0] == U.shape[0]
+    ny = Y.shape[1]
+    W = torch.empty((V.shape[0], ny), dtype=torch.float64, device=U.device)
+    if rows is not None:
+        rows = rows.to(torch.int64).contiguous()
+    _check(_lib.isvd_nc_fit(U.shape[0], V.shape[0], U.shape[1], ny, prec, _ptr(U), _ld(U), _ptr(S), _ptr(V), _ld(V),
+                            _ptr(Y), _ld(Y), _ptr(rows), -1 if rows is None else rows.shape[0], float(rcond),
+                            _ptr(W), ny, _stream()))
+    return W
 
 
 def exported_symbols_from_header(path=None):

@@ -239,7 +239,11 @@ isvd_status isvd_small_svd(int64_t n, const double* A, double* Uo, double* s, do
  * also return float U, V).  All pointers device, row-major.  Index arrays
  * are int64 and checked on the device: an index outside its range makes
  * the call return ISVD_E_INVALID (the outputs it touched are undefined).
- * These calls synchronise the stream before returning.
+ * isvd_ne_scores and isvd_nc_fit synchronise the stream before returning
+ * (isvd_ne_embeddings only enqueues its kernel).  isvd_ne_scores and
+ * isvd_nc_fit keep their device buffers in the library (one set per device,
+ * grown on demand, held until the process ends) and run one at a time per
+ * device (a host lock).
  * ------------------------------------------------------------------------ */
 
 /* Node embeddings of Eq. 5: L = U S^(1/2) (rows_u x k, ldl), R = V S^(1/2)
@@ -273,8 +277,9 @@ isvd_status isvd_nc_fit(int64_t rows_u, int64_t rows_v, int64_t k, int64_t ny, i
 
 /* on != 0: from now on every sparse pass is bracketed by a hipEvent pair on
  * its launch stream (two event records per pass, no host synchronisation; the
- * byte counts come from the host copy of the CSR sizes); the record is
- * cleared.  on == 0 stops recording. */
+ * byte counts come from the host copy of the CSR sizes), and so are the
+ * kernels of each learner call; the records are cleared.  on == 0 stops
+ * recording. */
 isvd_status isvd_profile_spmm_enable(int on);
 
 /* Totals over the passes recorded since the last enable/read (host outputs):
@@ -283,6 +288,13 @@ isvd_status isvd_profile_spmm_enable(int on);
  * and the number of passes.  Waits for the recorded events; clears the record. */
 isvd_status isvd_profile_spmm_read(double* total_ms, double* gather_bytes, double* compulsory_bytes,
                                    int64_t* launches);
+
+/* Totals of the learner calls recorded since the last enable/read (host
+ * arrays of 3: [0] isvd_ne_embeddings, [1] isvd_ne_scores, [2] isvd_nc_fit
+ * from its first kernel to its last): summed event durations in ms,
+ * algorithmic bytes (U, V, Y rows read once per use, outputs written once,
+ * indices), number of calls.  Waits for the events; clears the records. */
+isvd_status isvd_profile_learners_read(double* ms, double* bytes, int64_t* launches);
 
 /* ---------------------------------------------------------------------------
  * Learned warm start (not in the paper): a 16 -> 128 -> 128 -> k MLP with

@@ -1,9 +1,12 @@
 // extern "C" entry points: argument checks, exception barrier, last-error text.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "learners.h"
 #include "operator.h"
+#include "spmm.h"
 
 namespace isvd {
 
@@ -206,6 +209,23 @@ size_t learner_esize(isvd_precision p) {
              "learners take FP64 or FP32 factors (BF16 operators return FP32 U and V)");
   return p == ISVD_FP64 ? 8 : 4;
 }
+// Device buffers of the learner calls, one set per device, kept for the
+// life of the process (never freed: a static destructor would run after the
+// HIP runtime is gone).  A call holds its device's lock until it returns.
+struct LearnerWork {
+  std::mutex lock;
+  DevBuf bad, ug, yg, tm, work;
+};
+LearnerWork& learner_work() {
+  static std::mutex map_lock;
+  static std::map<int, LearnerWork*>* per_device = new std::map<int, LearnerWork*>();
+  int dev = 0;
+  ISVD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(map_lock);
+  LearnerWork*& w = (*per_device)[dev];
+  if (!w) w = new LearnerWork();
+  return *w;
+}
 // Waits for the stream and turns the device index flag into an error.
 void check_index_flag(const DevBuf& bad, hipStream_t s) {
   int flag = 0;
@@ -224,15 +244,20 @@ isvd_status isvd_ne_embeddings(int64_t rows_u, int64_t rows_v, int64_t k, isvd_p
     ISVD_CHECK(!L || (U && ldu >= k && ldl >= k), ISVD_E_INVALID, "bad L/U arguments");
     ISVD_CHECK(!R || (V && ldv >= k && ldr >= k), ISVD_E_INVALID, "bad R/V arguments");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    ISVD_CHECK(k <= 1024, ISVD_E_INVALID, "embeddings: k > 1024");
     const int kk = static_cast<int>(k);
-    if (precision == ISVD_FP64) {
-      if (L) launch_ne_embed<double>(rows_u, kk, static_cast<const double*>(U), ldu, S, static_cast<double*>(L), ldl, s);
-      if (R) launch_ne_embed<double>(rows_v, kk, static_cast<const double*>(V), ldv, S, static_cast<double*>(R), ldr, s);
-    } else {
-      if (L) launch_ne_embed<float>(rows_u, kk, static_cast<const float*>(U), ldu, S, static_cast<float*>(L), ldl, s);
-      if (R) launch_ne_embed<float>(rows_v, kk, static_cast<const float*>(V), ldv, S, static_cast<float*>(R), ldr, s);
-    }
-    ISVD_HIP(hipStreamSynchronize(s));
+    const int64_t n0 = L ? rows_u : 0, n1 = R ? rows_v : 0;
+    auto embed = [&](auto tag) {
+      using T = decltype(tag);
+      launch_ne_embed<T>(kk, S, n0, static_cast<const T*>(U), ldu, static_cast<T*>(L), ldl, n1,
+                         static_cast<const T*>(V), ldv, static_cast<T*>(R), ldr, s);
+    };
+    void* tok = spmm_profiling()
+                    ? profile_begin(1, s, 2.0 * static_cast<double>(n0 + n1) * k * learner_esize(precision), 0.0)
+                    : nullptr;
+    if (precision == ISVD_FP64) embed(double{});
+    else embed(float{});
+    if (tok) profile_end(s, tok);
     return ISVD_OK;
   });
 }
@@ -245,15 +270,22 @@ isvd_status isvd_ne_scores(int64_t k, isvd_precision precision, const void* U, i
     ISVD_CHECK(U && V && S && k >= 1 && ldu >= k && ldv >= k && npairs >= 0 && (npairs == 0 || (pi && pj && scores)),
                ISVD_E_INVALID, "bad score arguments");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    DevBuf bad;
+    LearnerWork& lw = learner_work();
+    std::lock_guard<std::mutex> hold(lw.lock);
+    DevBuf& bad = lw.bad;
     bad.ensure(sizeof(int));
     ISVD_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+    const double es = static_cast<double>(learner_esize(precision));
+    void* tok = spmm_profiling() && npairs > 0
+                    ? profile_begin(2, s, static_cast<double>(npairs) * (2.0 * k * es + 24.0), 0.0)
+                    : nullptr;
     if (precision == ISVD_FP64)
       launch_pair_scores<double>(static_cast<int>(k), static_cast<const double*>(U), ldu, rows_u, S,
                                  static_cast<const double*>(V), ldv, rows_v, npairs, pi, pj, scores, bad.as<int>(), s);
     else
       launch_pair_scores<float>(static_cast<int>(k), static_cast<const float*>(U), ldu, rows_u, S,
                                 static_cast<const float*>(V), ldv, rows_v, npairs, pi, pj, scores, bad.as<int>(), s);
+    if (tok) profile_end(s, tok);
     check_index_flag(bad, s);
     return ISVD_OK;
   });
@@ -272,7 +304,10 @@ isvd_status isvd_nc_fit(int64_t rows_u, int64_t rows_v, int64_t k, int64_t ny, i
     const bool subset = nsub >= 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int kk = static_cast<int>(k), yy = static_cast<int>(ny);
-    DevBuf bad, ug, yg, tm, work;
+    ISVD_CHECK(!subset || nsub == 0 || rows_u >= 1, ISVD_E_INVALID, "index out of range");
+    LearnerWork& lw = learner_work();
+    std::lock_guard<std::mutex> hold(lw.lock);
+    DevBuf &bad = lw.bad, &ug = lw.ug, &yg = lw.yg, &tm = lw.tm, &work = lw.work;
     bad.ensure(sizeof(int));
     ISVD_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
     const int64_t n = subset ? nsub : rows_u;
@@ -286,8 +321,8 @@ isvd_status isvd_nc_fit(int64_t rows_u, int64_t rows_v, int64_t k, int64_t ny, i
       if (subset && nsub > 0) {
         ug.ensure(static_cast<size_t>(std::max<int64_t>(nsub, 1)) * k * es);
         yg.ensure(static_cast<size_t>(std::max<int64_t>(nsub, 1)) * ny * es);
-        launch_gather_rows<T>(nsub, k, row_subset, rows_u, u, ldu, ug.as<T>(), k, bad.as<int>(), s);
-        launch_gather_rows<T>(nsub, ny, row_subset, rows_u, y, ldy, yg.as<T>(), ny, bad.as<int>(), s);
+        launch_gather_rows<T>(nsub, row_subset, rows_u, kk, u, ldu, ug.as<T>(), k, yy, y, ldy, yg.as<T>(), ny,
+                              bad.as<int>(), s);
         u = ug.as<T>();
         y = yg.as<T>();
         lu = k;
@@ -300,8 +335,13 @@ isvd_status isvd_nc_fit(int64_t rows_u, int64_t rows_v, int64_t k, int64_t ny, i
       launch_gram<T>(n, kk, yy, u, lu, y, ly, false, tm.as<double>(), ny, work.as<double>(), s);
       launch_nc_apply<T>(rows_v, kk, yy, static_cast<const T*>(V), ldv, S, rcond, tm.as<double>(), ny, W, ldw, s);
     };
+    // algorithmic bytes: the used rows of U and Y (and their indices) once, V once, W written
+    const double nb = static_cast<double>(n) * ((k + ny) * static_cast<double>(es) + (subset ? 8.0 : 0.0)) +
+                      static_cast<double>(rows_v) * (k * static_cast<double>(es) + 8.0 * ny);
+    void* tok = spmm_profiling() ? profile_begin(3, s, nb, 0.0) : nullptr;
     if (precision == ISVD_FP64) fit(double{});
     else fit(float{});
+    if (tok) profile_end(s, tok);
     check_index_flag(bad, s);
     return ISVD_OK;
   });
@@ -310,6 +350,15 @@ isvd_status isvd_nc_fit(int64_t rows_u, int64_t rows_v, int64_t k, int64_t ny, i
 isvd_status isvd_profile_spmm_enable(int on) {
   return guarded([&]() -> isvd_status {
     spmm_profile_enable(on != 0);
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_profile_learners_read(double* ms, double* bytes, int64_t* launches) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(ms && bytes && launches, ISVD_E_INVALID, "null output");
+    for (int c = 1; c < kProfileClasses; ++c)
+      profile_read(c, ms + c - 1, bytes + c - 1, nullptr, launches + c - 1);
     return ISVD_OK;
   });
 }

@@ -53,6 +53,7 @@ constexpr int kGramRB = 3;          // tiles per job side
 constexpr int kGramMaxWaves = 16;
 constexpr int kGramPF = 16;         // staged elements per thread per chunk
 constexpr int kGramMaxParts = 256;
+constexpr int kGramMinStageWaves = 8;
 constexpr size_t kGramMaxLds = 96 * 1024;
 
 template <typename TA, typename TB>
@@ -352,12 +353,22 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int m, int p, int npar
   const bool in = idx < static_cast<int64_t>(m) * p;
   const int a = in ? static_cast<int>(idx / p) : 0, b = in ? static_cast<int>(idx % p) : 0;
   const bool ok = in && (!same || a <= b);
-  double s = 0.0;
   const int64_t stride = static_cast<int64_t>(mp) * pp;
-  const int64_t off = static_cast<int64_t>(a) * pp + b;
-  if (ok)
-    for (int q = w; q < nparts; q += 4) s += partial[q * stride + off];
-  red[w][e] = s;
+  const double* src = partial + static_cast<int64_t>(a) * pp + b;
+  // four independent sums so that several partial loads are in flight
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (ok) {
+    int q = w;
+#pragma unroll 2
+    for (; q + 12 < nparts; q += 16) {
+      s0 += src[q * stride];
+      s1 += src[(q + 4) * stride];
+      s2 += src[(q + 8) * stride];
+      s3 += src[(q + 12) * stride];
+    }
+    for (; q < nparts; q += 4) s0 += src[q * stride];
+  }
+  red[w][e] = (s0 + s1) + (s2 + s3);
   __syncthreads();
   if (w == 0 && ok) {
     const double v = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
@@ -417,6 +428,9 @@ GramPlan plan_gram(int64_t rows, int m, int p, bool same, int esize, bool paired
   // halves of every chunk's k-steps, and their sums meet in LDS at the end.
   g.ksplit = (same && g.cs <= 4 && g.groups == 1 && g.njobs % 4 != 0 && 2 * g.njobs <= kGramMaxWaves) ? 2 : 1;
   g.waves *= g.ksplit;
+  // A^T B with few jobs (a narrow B): waves without a job still stage rows,
+  // so that each chunk is deep enough to hide the load latency
+  if (!same && g.groups == 1 && g.waves < kGramMinStageWaves) g.waves = kGramMinStageWaves;
   const int words = g.cs * g.vw * esize / 4 * (same ? 1 : 2);
   const int J = kGramPF / words > 0 ? kGramPF / words : 1;
   if (g.waves * J < 4) g.waves = static_cast<int>(ceil_div(4, J));   // at least one k-step per chunk

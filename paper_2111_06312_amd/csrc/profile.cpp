@@ -1,5 +1,7 @@
-// Opt-in per-launch timing of the sparse passes: a start/stop hipEvent pair on
-// the launch stream around every pass, plus the pass's algorithmic byte counts.
+// Opt-in per-launch timing: a start/stop hipEvent pair on the launch stream
+// around every timed region, plus its algorithmic byte counts.  Class 0 is
+// the sparse pass; classes 1..3 are the learner kernels (embeddings, pair
+// scores, the least-norm model chain).
 #include <mutex>
 #include <vector>
 
@@ -10,58 +12,75 @@ namespace isvd {
 namespace {
 struct Rec {
   hipEvent_t a = nullptr, b = nullptr;
-  double gather_bytes = 0.0, compulsory_bytes = 0.0;
+  double bytes = 0.0, bytes2 = 0.0;
+};
+struct Pool {
+  std::vector<Rec> recs;
+  size_t used = 0;
 };
 std::mutex g_mu;
 bool g_on = false;
-std::vector<Rec> g_pool;
-size_t g_used = 0;
+Pool g_pools[kProfileClasses];
 }  // namespace
 
 bool spmm_profiling() { return g_on; }
 
-void* spmm_profile_begin(hipStream_t stream, double gather_bytes, double compulsory_bytes) {
+void* profile_begin(int cls, hipStream_t stream, double bytes, double bytes2) {
   std::lock_guard<std::mutex> lk(g_mu);
-  if (g_used == g_pool.size()) {
+  Pool& p = g_pools[cls];
+  if (p.used == p.recs.size()) {
     Rec r;
     ISVD_HIP(hipEventCreate(&r.a));
     ISVD_HIP(hipEventCreate(&r.b));
-    g_pool.push_back(r);
+    p.recs.push_back(r);
   }
-  Rec& r = g_pool[g_used];
-  r.gather_bytes = gather_bytes;
-  r.compulsory_bytes = compulsory_bytes;
+  Rec& r = p.recs[p.used];
+  r.bytes = bytes;
+  r.bytes2 = bytes2;
   ISVD_HIP(hipEventRecord(r.a, stream));
-  return reinterpret_cast<void*>(++g_used);  // token = index + 1 (never null)
+  // token = class and index + 1 (never null)
+  return reinterpret_cast<void*>((static_cast<size_t>(cls) << 48) | ++p.used);
 }
 
-void spmm_profile_end(hipStream_t stream, void* token) {
+void profile_end(hipStream_t stream, void* token) {
   std::lock_guard<std::mutex> lk(g_mu);
-  ISVD_HIP(hipEventRecord(g_pool[reinterpret_cast<size_t>(token) - 1].b, stream));
+  const size_t t = reinterpret_cast<size_t>(token);
+  ISVD_HIP(hipEventRecord(g_pools[t >> 48].recs[(t & ((size_t(1) << 48) - 1)) - 1].b, stream));
 }
+
+void* spmm_profile_begin(hipStream_t stream, double gather_bytes, double compulsory_bytes) {
+  return profile_begin(0, stream, gather_bytes, compulsory_bytes);
+}
+
+void spmm_profile_end(hipStream_t stream, void* token) { profile_end(stream, token); }
 
 void spmm_profile_enable(bool on) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_on = on;
-  g_used = 0;
+  for (Pool& p : g_pools) p.used = 0;
+}
+
+void profile_read(int cls, double* ms, double* bytes, double* bytes2, int64_t* launches) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Pool& p = g_pools[cls];
+  double t = 0.0, b = 0.0, b2 = 0.0;
+  for (size_t i = 0; i < p.used; ++i) {
+    ISVD_HIP(hipEventSynchronize(p.recs[i].b));
+    float e = 0.f;
+    ISVD_HIP(hipEventElapsedTime(&e, p.recs[i].a, p.recs[i].b));
+    t += e;
+    b += p.recs[i].bytes;
+    b2 += p.recs[i].bytes2;
+  }
+  *ms = t;
+  *bytes = b;
+  if (bytes2) *bytes2 = b2;
+  *launches = static_cast<int64_t>(p.used);
+  p.used = 0;
 }
 
 void spmm_profile_read(double* ms, double* gather, double* compulsory, int64_t* launches) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  double t = 0.0, gb = 0.0, cb = 0.0;
-  for (size_t i = 0; i < g_used; ++i) {
-    ISVD_HIP(hipEventSynchronize(g_pool[i].b));
-    float e = 0.f;
-    ISVD_HIP(hipEventElapsedTime(&e, g_pool[i].a, g_pool[i].b));
-    t += e;
-    gb += g_pool[i].gather_bytes;
-    cb += g_pool[i].compulsory_bytes;
-  }
-  *ms = t;
-  *gather = gb;
-  *compulsory = cb;
-  *launches = static_cast<int64_t>(g_used);
-  g_used = 0;
+  profile_read(0, ms, gather, compulsory, launches);
 }
 
 }  // namespace isvd

@@ -52,6 +52,13 @@ void spmm_profile_end(hipStream_t stream, void* token);
 void spmm_profile_enable(bool on);
 void spmm_profile_read(double* ms, double* gather, double* compulsory, int64_t* launches);
 
+// Timed regions of other kernels (classes 1 .. kProfileClasses - 1), recorded
+// while spmm_profiling() is on.
+constexpr int kProfileClasses = 4;
+void* profile_begin(int cls, hipStream_t stream, double bytes, double bytes2);
+void profile_end(hipStream_t stream, void* token);
+void profile_read(int cls, double* ms, double* bytes, double* bytes2, int64_t* launches);
+
 // Launch one pass; T = storage type (double, float, bf16).
 template <typename T>
 void launch_spmm_pass(const SpmmPass& p, hipStream_t stream);

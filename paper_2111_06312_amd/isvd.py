@@ -108,6 +108,7 @@ def load():
     lib.isvd_nc_fit.argtypes = [i64, i64, i64, i64, st, vp, i64, vp, vp, i64, vp, i64, vp, i64, ct.c_double,
                                 vp, i64, vp]
     lib.isvd_profile_spmm_enable.argtypes = [st]
+    lib.isvd_profile_learners_read.argtypes = [vp, vp, vp]
     lib.isvd_profile_spmm_read.argtypes = [ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
                                            ct.POINTER(ct.c_double), ct.POINTER(i64)]
     _lib = lib
@@ -228,6 +229,17 @@ def profile_spmm_read():
     ms, gb, cb, n = ct.c_double(), ct.c_double(), ct.c_double(), ct.c_int64()
     _check(_lib.isvd_profile_spmm_read(ct.byref(ms), ct.byref(gb), ct.byref(cb), ct.byref(n)))
     return ms.value, gb.value, cb.value, n.value
+
+
+def profile_learners_read():
+    """{name: (ms, algorithmic bytes, calls)} of the learner calls recorded
+    since profile_spmm(True) or the last read."""
+    ms = (ct.c_double * 3)()
+    by = (ct.c_double * 3)()
+    n = (ct.c_int64 * 3)()
+    _check(_lib.isvd_profile_learners_read(ct.cast(ms, ct.c_void_p), ct.cast(by, ct.c_void_p),
+                                           ct.cast(n, ct.c_void_p)))
+    return {name: (ms[i], by[i], n[i]) for i, name in enumerate(("ne_embeddings", "ne_scores", "nc_fit"))}
 
 
 def gaussian_block(rows, cols, seed, dtype=torch.float32, device="cuda"):

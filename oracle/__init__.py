@@ -11,15 +11,16 @@ checked against the paper by eye:
 
 - graph.py      : A, D, the transition matrix T = D^-1 A and the
                   symmetrically normalised A_hat (Section 2).
-- operators.py  : products with the design matrices M^(NE) (Eq. 2 with
-                  explicit weights, Fig. 1) and M^(NC) (Eq. 6), and with
-                  their transposes, by the naive power sum.
+- operators.py  : products with the design matrices M^(NE) (Eq. 3 with
+                  explicit weights, Fig. 1) and M^(NC) (Eq. 7), and with
+                  their transposes, by the naive power sum; the
+                  implicit row gather M[rows, :] (Section 3.2, option (ii)).
 - isvd.py       : Algorithm 1 (randomized SVD of an implicit matrix) with
                   Householder QR or Cholesky orthonormalisation
                   (Algorithm 2), and the per-triplet residual.
 - learners.py   : the closed-form learners on the SVD: node embeddings and
                   pair scores (Eq. 5) and the least-norm model
-                  W* = V S^+ U^T Y (Eq. 7, Theorem 1).
+                  W* = V S^+ U^T Y (Eq. 8, Theorem 1).
 - mlp.py        : the warm-start network, its subspace loss and a
                   hand-derived backward pass.
 - philox.py     : the Philox4x32-10 counter-based generator and the

@@ -37,7 +37,7 @@ def transition(a: sp.csr_matrix) -> sp.csr_matrix:
 
     A node with zero degree has an all-zero row of A; its row of T is left
     zero (D^-1 read as the pseudo-inverse of D, the same convention as the
-    S^+ of Eq. 7)."""
+    S^+ of Eq. 8)."""
     d = degrees(a)
     dinv = np.zeros_like(d)
     nz = d != 0

@@ -4,7 +4,7 @@ Test infrastructure only (see the package docstring).
 
 - Node embeddings (Eq. 5): L = U S^(1/2), R = V S^(1/2); the score of the
   node pair (i, j) is <L_i, R_j> = U_i^T S V_j.
-- Least-norm linear model (Eq. 7): W* = V S^+ U^T Y, multiplied right to
+- Least-norm linear model (Eq. 8): W* = V S^+ U^T Y, multiplied right to
   left; S^+ reciprocates the non-zero singular values.  With labels on a
   subset of rows only, option (i) of Section 3.2 takes that subset of the
   rows of both U and Y.  Theorem 1: when k >= rank(M), W* is the
@@ -43,7 +43,7 @@ def s_pinv(s: np.ndarray, rcond: float = 0.0) -> np.ndarray:
 
 
 def nc_fit(u: np.ndarray, s: np.ndarray, v: np.ndarray, y: np.ndarray, rows=None, rcond: float = 0.0) -> np.ndarray:
-    """W* = V S^+ U^T Y (Eq. 7), right to left; `rows` keeps the labelled rows
+    """W* = V S^+ U^T Y (Eq. 8), right to left; `rows` keeps the labelled rows
     of U and Y (option (i))."""
     if rows is not None:
         u = u[rows]

@@ -19,9 +19,9 @@ from .graph import adjacency, sym_normalized, transition
 
 
 class NEDesignMatrix:
-    """M = sum_{j=1..K} c_j T^j - lambda (1 1^T - A), n x n (Eq. 2, Fig. 1).
+    """M = sum_{j=1..K} c_j T^j - lambda (1 1^T - A), n x n (Eq. 3, Fig. 1).
 
-    Eq. 2 takes the expectation of T^q under the context distribution; its
+    Eq. 3 takes the expectation of T^q under the context distribution; its
     weights are passed explicitly as `coeffs` = (c_1, ..., c_K) (the
     workloads use c_j = 1/K; Fig. 1 uses (3, 2, 1)/6).  "1" in the
     lambda term is the all-ones n x n matrix (Fig. 1 builds it as the
@@ -70,7 +70,7 @@ class NEDesignMatrix:
 
 
 class FeatPropDesignMatrix:
-    """M = [X, A_hat X, A_hat^2 X, ..., A_hat^L X], n x d(L+1) (Eq. 6).
+    """M = [X, A_hat X, A_hat^2 X, ..., A_hat^L X], n x d(L+1) (Eq. 7).
 
     The blocks B_j = A_hat^j X are materialised here (the oracle may hold
     M explicitly); M G = sum_j B_j G_j over the row blocks G_j of G, and
@@ -123,6 +123,36 @@ class FeatPropDesignMatrix:
     def dense(self) -> np.ndarray:
         m = np.hstack(self.blocks)
         return m.T if self.transposed else m
+
+
+class RowGather:
+    """M_sub = M[rows, :] of an implicit M, without forming either (the
+    implicit row gather of Section 3.2, option (ii), and Section 4).
+
+    M_sub G takes the listed rows of M G; M_sub^T Q = M^T Q' where Q' has
+    the rows of Q at the listed positions and zeros elsewhere (rows are
+    distinct).
+    """
+
+    def __init__(self, m, rows, transposed: bool = False):
+        self.m = m
+        self.rows = np.asarray(rows, dtype=np.int64)
+        assert self.rows.ndim == 1 and len(np.unique(self.rows)) == len(self.rows)
+        self.transposed = transposed
+        full = (len(self.rows), m.shape[1])
+        self.shape = full[::-1] if transposed else full
+
+    @property
+    def T(self) -> "RowGather":
+        return RowGather(self.m, self.rows, not self.transposed)
+
+    def dot(self, g):
+        g = np.asarray(g, dtype=np.float64)
+        if not self.transposed:
+            return self.m.dot(g)[self.rows]
+        q = np.zeros((self.m.shape[0],) + g.shape[1:])
+        q[self.rows] = g
+        return self.m.T.dot(q)
 
 
 def context_weights(C: int) -> np.ndarray:

@@ -12,7 +12,7 @@ import pytest
 import scipy.sparse as sp
 
 from oracle.graph import adjacency, degrees, sym_normalized, transition
-from oracle.operators import FeatPropDesignMatrix, NEDesignMatrix, context_weights
+from oracle.operators import FeatPropDesignMatrix, NEDesignMatrix, RowGather, context_weights
 from synth import complete_graph, cycle_graph
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
@@ -62,7 +62,7 @@ def test_fig1_weights_are_printed_values():
 
 
 def test_eq2_printed_weights_sum_to_one_over_C():
-    # The weights as printed in Eq. 2, (2/((C+1)C)) (C-q+1)/C, sum to 1/C, not 1:
+    # The weights as printed in Eq. 3, (2/((C+1)C)) (C-q+1)/C, sum to 1/C, not 1:
     # the reason the coefficients are taken as explicit inputs.
     for C in (3, 5, 10):
         w = [(2.0 / ((C + 1) * C)) * (C - q + 1) / C for q in range(1, C + 1)]
@@ -215,3 +215,26 @@ def test_adjacency_self_loops_enter_degree_and_lambda_term():
     assert np.allclose(np.diag(dense), 1.0 / 3.0)
     # non-neighbours: -lambda
     assert abs(dense[0, 2] + 0.5) < 1e-15
+
+
+@pytest.mark.parametrize("form", ["ne", "featprop"])
+def test_row_gather_is_the_row_submatrix(form):
+    # Section 3.2 option (ii): M[rows, :] without forming M; checked against
+    # the explicit matrix built column by column from unit vectors
+    rng = np.random.default_rng(11)
+    n = 40
+    a = sp.random(n, n, density=0.1, random_state=12, format="csr")
+    a = ((a + a.T) > 0).astype(np.float64).tocsr()
+    if form == "ne":
+        m = NEDesignMatrix(a, [0.5, 0.3, 0.2], 0.07)
+    else:
+        m = FeatPropDesignMatrix(a, rng.standard_normal((n, 3)), 2)
+    rows = rng.choice(n, 13, replace=False)
+    sub = RowGather(m, rows)
+    assert sub.shape == (13, m.shape[1]) and sub.T.shape == (m.shape[1], 13)
+    full = _explicit(m)
+    assert np.allclose(_explicit(sub), full[rows], atol=1e-13)
+    assert np.allclose(_explicit(sub.T), full[rows].T, atol=1e-13)
+    # repeated rows are refused (the transpose scatters without adding)
+    with pytest.raises(AssertionError):
+        RowGather(m, [1, 2, 1])

@@ -53,7 +53,7 @@ def parse():
                          "start block are timed for comparison")
     ap.add_argument("--learners", action="store_true",
                     help="time the closed-form learners instead: Eq. 5 embeddings and pair scores on the "
-                         "rank-128 SVD of the n = 200,000 NE workload, and the Eq. 7 least-norm model on the "
+                         "rank-128 SVD of the n = 200,000 NE workload, and the Eq. 8 least-norm model on the "
                          "rank-64 SVD of the n = 170,000 feature-propagation workload (one JSON line)")
     ap.add_argument("--pairs", type=int, default=2_000_000)
     ap.add_argument("--label-frac", type=float, default=0.5)
@@ -83,7 +83,7 @@ def learners_bench(args, lib, torch, np):
 
     NE (Eq. 5): U, S, V of the n = 200,000 Chung-Lu NE matrix (k = 128,
     FP32); embeddings L, R and `--pairs` uniform random pair scores.  NC
-    (Eq. 7): U, S, V of the n = 170,000 SBM feature-propagation matrix
+    (Eq. 8): U, S, V of the n = 170,000 SBM feature-propagation matrix
     (d = 128, L = 3, k = 64, FP32), labels = the 40 planted blocks one-hot,
     `--label-frac` of the rows labelled (option (i)).  `value` sums the
     host-clocked call times (they include each call's synchronisation);
@@ -138,7 +138,7 @@ def learners_bench(args, lib, torch, np):
                      "gbps": round(b_nc / t_nc / 1e9, 1)}
     dom = max(out, key=lambda key: out[key]["s"])     # longest device time
     line = {
-        "metric": "closed-form learner time on resident SVD outputs (Eq. 5 and Eq. 7)",
+        "metric": "closed-form learner time on resident SVD outputs (Eq. 5 and Eq. 8)",
         "value": round(sum(v["call_s"] for v in out.values()), 6), "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "vs_baseline": None,
         "dtype": "f32 in, f64 sums", "data": "synthetic",

@@ -11,10 +11,10 @@
  * Two design-matrix forms are built in:
  *   ISVD_FORM_NE       M = sum_{j=1..K} c_j T^j - lambda (1 1^T - A),  n x n
  *                      with T = D^-1 A (Section 2) and explicit weights c_j
- *                      (Eq. 2 takes an expectation over walk lengths; Fig. 1
+ *                      (Eq. 3 takes an expectation over walk lengths; Fig. 1
  *                      builds the same matrix symbolically).
  *   ISVD_FORM_FEATPROP M = [X, Ahat X, Ahat^2 X, ..., Ahat^L X],  n x d(L+1)
- *                      with Ahat = (D+I)^-1/2 (A+I) (D+I)^-1/2 (Section 2, Eq. 6).
+ *                      with Ahat = (D+I)^-1/2 (A+I) (D+I)^-1/2 (Section 2, Eq. 7).
  *
  * Conventions (all entry points):
  *  - Every array argument is DEVICE memory unless its comment says "host".
@@ -119,6 +119,19 @@ void isvd_destroy_operator(isvd_operator* op);
 
 /* (rows, cols) of M: (n, n) for NE, (n, d(L+1)) for FEATPROP (host outputs). */
 isvd_status isvd_operator_shape(const isvd_operator* op, int64_t* rows, int64_t* cols);
+
+/* Implicit row gather (Section 3.2, option (ii); Section 4): restricts the
+ * operator to M[rows, :] (say, the rows of the labelled nodes) without
+ * forming M or the submatrix.  rows: nsub distinct device int64 indices in
+ * [0, n) (copied; the caller may free its array after the call); rows ==
+ * NULL restores M.  Afterwards isvd_operator_shape reports nsub rows and
+ * isvd_matmul_block / isvd_truncated_svd work on M[rows, :]: the forward
+ * product computes M Y and keeps the selected rows; the transpose places
+ * the nsub-row block at the selected rows of an n-row zero block first
+ * (workspace: one n x ncols block).  An index out of range or repeated:
+ * ISVD_E_INVALID, and the operator is left unrestricted.  Synchronises the
+ * stream. */
+isvd_status isvd_operator_gather_rows(isvd_operator* op, const int64_t* rows, int64_t nsub, void* stream);
 
 /* out = M * Y (transpose == 0; Y is cols x ncols, out is rows x ncols) or
  * out = M^T * Y (transpose != 0; Y is rows x ncols, out is cols x ncols)
@@ -258,7 +271,7 @@ isvd_status isvd_ne_scores(int64_t k, isvd_precision precision, const void* U, i
                            const double* S, const void* V, int64_t ldv, int64_t rows_v, int64_t npairs,
                            const int64_t* pi, const int64_t* pj, double* scores, void* stream);
 
-/* Least-norm linear model of Eq. 7 (Theorem 1): W = V S^+ U^T Y, multiplied
+/* Least-norm linear model of Eq. 8 (Theorem 1): W = V S^+ U^T Y, multiplied
  * right to left: U^T Y (FP64 sums of exact products, k + ny <= 2048), then
  * S^+ (1/s_t for s_t > rcond * max(S), else 0; rcond = 0 is the literal
  * rule), then V.  Y: rows_u x ny, the element type of U.  nsub >= 0:

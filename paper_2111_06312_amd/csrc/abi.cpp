@@ -96,6 +96,14 @@ isvd_status isvd_operator_shape(const isvd_operator* op, int64_t* rows, int64_t*
   });
 }
 
+isvd_status isvd_operator_gather_rows(isvd_operator* op, const int64_t* rows, int64_t nsub, void* stream) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(op, ISVD_E_INVALID, "null operator");
+    select_rows(op, rows, nsub, static_cast<hipStream_t>(stream));
+    return ISVD_OK;
+  });
+}
+
 isvd_status isvd_matmul_block(isvd_operator* op, int transpose, const void* Y, int64_t ldy, int64_t ncols,
                               void* out, int64_t ldo, void* stream) {
   return guarded([&]() -> isvd_status {

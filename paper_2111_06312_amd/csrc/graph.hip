@@ -1,5 +1,7 @@
 // Graph ingest kernels: self-loop CSR, degrees, D^-1 and (D+I)^-1/2 scales,
 // hub-row lists, and the small rearrangements of the feature form.
+#include <algorithm>
+
 #include "operator.h"
 
 namespace isvd {
@@ -92,9 +94,92 @@ __global__ void side_to_stack_kernel(int d, int L1, int l, const double* Cm, int
   Elem<T>::store(out + static_cast<int64_t>(j * d + a) * ldo + c, static_cast<C>(Cm[static_cast<int64_t>(a) * ldc + rem]));
 }
 
+// Row selection of an implicit row gather: pos[i] = r for i = rows[r], -1
+// for rows not selected.  flag |= 1 for an index out of range, 2 for a
+// repeated index.
+__global__ void fill_pos_kernel(int64_t n, int32_t* pos) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) pos[i] = -1;
+}
+__global__ void select_rows_kernel(int64_t nsel, const int64_t* rows, int64_t n, int32_t* pos, int* flag) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nsel) return;
+  const int64_t i = rows[r];
+  if (i < 0 || i >= n) {
+    atomicOr(flag, 1);
+    return;
+  }
+  if (atomicCAS(pos + i, -1, static_cast<int32_t>(r)) != -1) atomicOr(flag, 2);
+}
+
+// dst[r] = src[rows[r]] (ncols elements per row): one wave per row.
+template <typename T>
+__global__ __launch_bounds__(256) void gather_block_kernel(int64_t nsel, int ncols, const int64_t* rows, const T* src,
+                                                           int64_t lds, T* dst, int64_t ldd) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; r < nsel;
+       r += (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6) {
+    const T* a = src + rows[r] * lds;
+    T* o = dst + r * ldd;
+    for (int c = lane; c < ncols; c += 64) o[c] = a[c];
+  }
+}
+
+// dst[i] = src[pos[i]] for selected rows, zeros for the others (every one of
+// the n rows written once): one wave per row.
+template <typename T>
+__global__ __launch_bounds__(256) void scatter_block_kernel(int64_t n, int ncols, const int32_t* pos, const T* src,
+                                                            int64_t lds, T* dst, int64_t ldd) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; i < n;
+       i += (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6) {
+    const int32_t p = pos[i];
+    T* o = dst + i * ldd;
+    if (p >= 0) {
+      const T* a = src + static_cast<int64_t>(p) * lds;
+      for (int c = lane; c < ncols; c += 64) o[c] = a[c];
+    } else {
+      for (int c = lane; c < ncols; c += 64) o[c] = T{};
+    }
+  }
+}
+
 unsigned blocks_for(int64_t n, int t = 256) { return static_cast<unsigned>(ceil_div(n > 0 ? n : 1, t)); }
 
+unsigned row_wave_blocks(int64_t rows) { return static_cast<unsigned>(std::min<int64_t>(ceil_div(rows, 4), 16384)); }
+
 }  // namespace
+
+void build_row_selection(int64_t n, int64_t nsel, const int64_t* rows, int32_t* pos, int* flag, hipStream_t stream) {
+  hipLaunchKernelGGL(fill_pos_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, n, pos);
+  ISVD_LAUNCH_CHECK();
+  if (nsel == 0) return;
+  hipLaunchKernelGGL(select_rows_kernel, dim3(blocks_for(nsel)), dim3(256), 0, stream, nsel, rows, n, pos, flag);
+  ISVD_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_gather_block(int64_t nsel, int ncols, const int64_t* rows, const T* src, int64_t lds, T* dst,
+                         int64_t ldd, hipStream_t stream) {
+  if (nsel == 0) return;
+  hipLaunchKernelGGL(gather_block_kernel<T>, dim3(row_wave_blocks(nsel)), dim3(256), 0, stream, nsel, ncols, rows,
+                     src, lds, dst, ldd);
+  ISVD_LAUNCH_CHECK();
+}
+template void launch_gather_block<double>(int64_t, int, const int64_t*, const double*, int64_t, double*, int64_t, hipStream_t);
+template void launch_gather_block<float>(int64_t, int, const int64_t*, const float*, int64_t, float*, int64_t, hipStream_t);
+template void launch_gather_block<bf16>(int64_t, int, const int64_t*, const bf16*, int64_t, bf16*, int64_t, hipStream_t);
+
+template <typename T>
+void launch_scatter_block(int64_t n, int ncols, const int32_t* pos, const T* src, int64_t lds, T* dst, int64_t ldd,
+                          hipStream_t stream) {
+  hipLaunchKernelGGL(scatter_block_kernel<T>, dim3(row_wave_blocks(n)), dim3(256), 0, stream, n, ncols, pos, src,
+                     lds, dst, ldd);
+  ISVD_LAUNCH_CHECK();
+}
+template void launch_scatter_block<double>(int64_t, int, const int32_t*, const double*, int64_t, double*, int64_t, hipStream_t);
+template void launch_scatter_block<float>(int64_t, int, const int32_t*, const float*, int64_t, float*, int64_t, hipStream_t);
+template void launch_scatter_block<bf16>(int64_t, int, const int32_t*, const bf16*, int64_t, bf16*, int64_t, hipStream_t);
 
 void build_loop_csr(int64_t n, const int64_t* indptr, const int32_t* indices, const float* values,
                     int64_t nnz, DevBuf& out_ptr, DevBuf& out_idx, DevBuf& out_val, hipStream_t stream) {

@@ -1,5 +1,5 @@
 // Closed-form learners on a rank-k SVD (Section 3): node embeddings and pair
-// scores (Eq. 5), and the least-norm linear model W* = V S^+ U^T Y (Eq. 7),
+// scores (Eq. 5), and the least-norm linear model W* = V S^+ U^T Y (Eq. 8),
 // multiplied right to left.  Index arrays are checked on the device: an index
 // out of range writes NaN where it was used and raises a flag the entry point
 // turns into ISVD_E_INVALID (no access outside the arrays).

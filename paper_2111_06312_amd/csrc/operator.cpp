@@ -1,6 +1,6 @@
 // Products with the implicit design matrices as fused Horner passes.
 //
-// NE form, M = sum_{j=1..K} c_j T^j - lambda (1 1^T - A), T = D^-1 A (Eq. 2).
+// NE form, M = sum_{j=1..K} c_j T^j - lambda (1 1^T - A), T = D^-1 A (Eq. 3).
 // With P = A Y, T^j Y = D^-1 (A D^-1)^(j-1) P, so
 //     sum_j c_j T^j Y = D^-1 W_1,   W_K = c_K P,   W_j = c_j P + A D^-1 W_{j+1}.
 // Storing W'_j = D^-1 W_j makes every pass a plain gather with A:
@@ -14,7 +14,7 @@
 // again K passes; the first gathers Y with the column scale c_K / d_j.
 // 1^T Y is summed in FP64 once per product.
 //
-// Feature form, M = [X, Ah X, ..., Ah^L X], Ah = (D+I)^-1/2 (A+I) (D+I)^-1/2 (Eq. 6):
+// Feature form, M = [X, Ah X, ..., Ah^L X], Ah = (D+I)^-1/2 (A+I) (D+I)^-1/2 (Eq. 7):
 //     M G = X G_0 + Ah (X G_1 + Ah (... + Ah X G_L))  : one GEMM X [G_0..G_L], then L passes
 //     M^T Q = [X^T P_0; ...; X^T P_L], P_0 = Q, P_j = Ah^T P_{j-1} : L passes, one X^T [P] Gram
 #include "operator.h"
@@ -220,12 +220,64 @@ void setup_csr(isvd_operator* op, Csr& csr, const int64_t* indptr, const int32_t
 
 }  // namespace
 
+namespace {
 template <typename T>
-void apply_operator(isvd_operator* op, bool transpose, const T* Y, int64_t ldy, int ncols, T* out,
-                    int64_t ldo, hipStream_t stream, const double* colsum_y) {
+void apply_full(isvd_operator* op, bool transpose, const T* Y, int64_t ldy, int ncols, T* out, int64_t ldo,
+                hipStream_t stream, const double* colsum_y) {
   if (op->form == ISVD_FORM_NE) apply_ne<T>(op, transpose, Y, ldy, ncols, out, ldo, stream, colsum_y);
   else apply_featprop<T>(op, transpose, Y, ldy, ncols, out, ldo, stream);
 }
+}  // namespace
+
+// With a row gather, M_sub = M[rows, :]: M_sub Y is the full product's
+// selected rows; M_sub^T Y = M^T Y' with Y' = Y's rows at the selected
+// positions and zeros elsewhere (1^T Y' = 1^T Y, so colsum_y carries over).
+template <typename T>
+void apply_operator(isvd_operator* op, bool transpose, const T* Y, int64_t ldy, int ncols, T* out,
+                    int64_t ldo, hipStream_t stream, const double* colsum_y) {
+  if (op->nsel < 0) return apply_full<T>(op, transpose, Y, ldy, ncols, out, ldo, stream, colsum_y);
+  const int64_t ldb = block_ld(ncols);
+  op->sel_block.ensure(static_cast<size_t>(op->n) * ldb * sizeof(T));
+  T* blk = op->sel_block.as<T>();
+  if (!transpose) {
+    apply_full<T>(op, false, Y, ldy, ncols, blk, ldb, stream, colsum_y);
+    launch_gather_block<T>(op->nsel, ncols, op->sel_rows.as<int64_t>(), blk, ldb, out, ldo, stream);
+  } else {
+    launch_scatter_block<T>(op->n, ncols, op->sel_pos.as<int32_t>(), Y, ldy, blk, ldb, stream);
+    apply_full<T>(op, true, blk, ldb, ncols, out, ldo, stream, colsum_y);
+  }
+}
+
+void select_rows(isvd_operator* op, const int64_t* rows, int64_t nsel, hipStream_t stream) {
+  if (!rows) {
+    op->nsel = -1;
+    op->rows = op->n;
+    op->sel_rows.release();
+    op->sel_pos.release();
+    op->sel_block.release();
+    return;
+  }
+  ISVD_CHECK(nsel >= 1 && nsel <= op->n, ISVD_E_INVALID, "row gather: need 1 <= nsub <= n");
+  DevBuf flag;
+  flag.ensure(sizeof(int));
+  ISVD_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), stream));
+  op->sel_rows.ensure(static_cast<size_t>(nsel) * sizeof(int64_t));
+  ISVD_HIP(hipMemcpyAsync(op->sel_rows.p, rows, static_cast<size_t>(nsel) * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                          stream));
+  op->sel_pos.ensure(static_cast<size_t>(op->n) * sizeof(int32_t));
+  build_row_selection(op->n, nsel, op->sel_rows.as<int64_t>(), op->sel_pos.as<int32_t>(), flag.as<int>(), stream);
+  int f = 0;
+  ISVD_HIP(hipMemcpyAsync(&f, flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+  ISVD_HIP(hipStreamSynchronize(stream));
+  if (f != 0) {
+    op->nsel = -1;
+    op->rows = op->n;
+    throw Error{ISVD_E_INVALID, (f & 1) ? "row gather: index out of range" : "row gather: repeated index"};
+  }
+  op->nsel = nsel;
+  op->rows = nsel;
+}
+
 template void apply_operator<double>(isvd_operator*, bool, const double*, int64_t, int, double*, int64_t, hipStream_t, const double*);
 template void apply_operator<float>(isvd_operator*, bool, const float*, int64_t, int, float*, int64_t, hipStream_t, const double*);
 template void apply_operator<bf16>(isvd_operator*, bool, const bf16*, int64_t, int, bf16*, int64_t, hipStream_t, const double*);

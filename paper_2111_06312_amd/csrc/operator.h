@@ -19,6 +19,16 @@ template <typename C>
 void build_row_scale(int64_t n, const int64_t* indptr, const float* values, int mode, double* deg, C* scale,
                      hipStream_t stream);
 int64_t build_heavy_rows(int64_t n, const int64_t* indptr, int64_t threshold, DevBuf& list, hipStream_t stream);
+// Implicit row gather: pos (n int32) from the selected rows (flag |= 1: an
+// index out of range, |= 2: a repeated index); gather of the selected rows;
+// scatter back into n rows with zeros elsewhere.
+void build_row_selection(int64_t n, int64_t nsel, const int64_t* rows, int32_t* pos, int* flag, hipStream_t stream);
+template <typename T>
+void launch_gather_block(int64_t nsel, int ncols, const int64_t* rows, const T* src, int64_t lds, T* dst,
+                         int64_t ldd, hipStream_t stream);
+template <typename T>
+void launch_scatter_block(int64_t n, int ncols, const int32_t* pos, const T* src, int64_t lds, T* dst, int64_t ldd,
+                          hipStream_t stream);
 template <typename T, typename C>
 void launch_stack_to_side(int d, int L1, int l, const T* G, int64_t ldg, C* B, int64_t ldb, hipStream_t stream);
 template <typename T>
@@ -53,6 +63,10 @@ struct isvd_operator {
   const void* X = nullptr;
   int64_t d = 0, ldx = 0;
   int L = 0;
+  // implicit row gather (rows = nsel < 0: none): the selected rows, their
+  // positions, and an n-row block for the full product / scattered input
+  int64_t nsel = -1;
+  isvd::DevBuf sel_rows, sel_pos, sel_block;
   // workspace of the products
   isvd::DevBuf tmp[3];
   isvd::DevBuf colsum_part, svec, gram_work, side_c, side_b;
@@ -73,6 +87,10 @@ namespace isvd {
 template <typename T>
 void apply_operator(isvd_operator* op, bool transpose, const T* Y, int64_t ldy, int ncols, T* out,
                     int64_t ldo, hipStream_t stream, const double* colsum_y = nullptr);
+
+// Restricts the operator to M[rows, :] (rows: nsel distinct device indices,
+// copied) or, with rows == NULL, back to M.  Synchronises the stream.
+void select_rows(isvd_operator* op, const int64_t* rows, int64_t nsel, hipStream_t stream);
 
 void create_operator(const isvd_graph* g, const isvd_design* m, isvd_precision prec, hipStream_t stream,
                      isvd_operator* op);

@@ -86,6 +86,7 @@ def load():
     lib.isvd_destroy_operator.argtypes = [vp]
     lib.isvd_destroy_operator.restype = None
     lib.isvd_operator_shape.argtypes = [vp, ct.POINTER(i64), ct.POINTER(i64)]
+    lib.isvd_operator_gather_rows.argtypes = [vp, vp, i64, vp]
     lib.isvd_matmul_block.argtypes = [vp, st, vp, i64, i64, vp, i64, vp]
     lib.isvd_truncated_svd.argtypes = [vp, ct.POINTER(_SvdParams), vp, i64, vp, vp, i64, ct.POINTER(_SvdInfo), vp]
     lib.isvd_gaussian_block.argtypes = [i64, i64, ct.c_uint64, st, vp, i64, vp]
@@ -183,6 +184,21 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+    def gather_rows(self, rows=None):
+        """Restrict to M[rows, :] (distinct int64 indices; a device copy is
+        taken) or, with rows=None, back to M (isvd_operator_gather_rows)."""
+        try:
+            if rows is None:
+                _check(_lib.isvd_operator_gather_rows(self.handle, None, 0, _stream()))
+            else:
+                r = torch.as_tensor(rows, dtype=torch.int64, device=self._indptr.device).contiguous()
+                _check(_lib.isvd_operator_gather_rows(self.handle, _ptr(r), r.shape[0], _stream()))
+        finally:
+            nr, nc = ct.c_int64(), ct.c_int64()
+            _check(_lib.isvd_operator_shape(self.handle, ct.byref(nr), ct.byref(nc)))
+            self.shape = (nr.value, nc.value)
+        return self
 
     def matmul(self, Y, transpose=False, out=None):
         """M @ Y (or M^T @ Y) through isvd_matmul_block; enqueued on the current stream."""
@@ -313,7 +329,7 @@ def ne_scores(U, S, V, pi, pj):
 
 
 def nc_fit(U, S, V, Y, rows=None, rcond=0.0):
-    """Least-norm W = V S^+ U^T Y of Eq. 7 (FP64, V.shape[0] x Y.shape[1]).
+    """Least-norm W = V S^+ U^T Y of Eq. 8 (FP64, V.shape[0] x Y.shape[1]).
 
     Y has the dtype of U; rows (int64 device tensor) keeps only those rows of
     U and Y (the labelled nodes)."""

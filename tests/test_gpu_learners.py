@@ -1,5 +1,5 @@
 """Parity of the closed-form learners (Section 3: Eq. 5 embeddings and pair
-scores, Eq. 7 least-norm model) with the FP64 oracle, through the C-ABI.
+scores, Eq. 8 least-norm model) with the FP64 oracle, through the C-ABI.
 
 Bounds: the device sums exact FP64 products in another order than numpy, so
 each output is checked against c * eps64 * (the same sum over |terms|).
@@ -132,7 +132,7 @@ def test_nc_fit_edges(gpu_lib):
 
 
 def test_featprop_svd_then_least_norm_model(gpu_lib):
-    # L = 0 and k = d: M = X exactly, so Eq. 7 on the device SVD gives the
+    # L = 0 and k = d: M = X exactly, so Eq. 8 on the device SVD gives the
     # least-norm least-squares solution of X W = Y (Theorem 1).
     _case("featprop + nc_fit")
     cfg = CONFIGS["c3"].scaled(4000)

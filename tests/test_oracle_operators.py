@@ -61,7 +61,7 @@ def test_fig1_weights_are_printed_values():
         assert abs(context_weights(C).sum() - 1.0) < 1e-15
 
 
-def test_eq2_printed_weights_sum_to_one_over_C():
+def test_eq3_printed_weights_sum_to_one_over_C():
     # The weights as printed in Eq. 3, (2/((C+1)C)) (C-q+1)/C, sum to 1/C, not 1:
     # the reason the coefficients are taken as explicit inputs.
     for C in (3, 5, 10):

@@ -15,6 +15,10 @@ checked against the paper by eye:
                   explicit weights, Fig. 1) and M^(NC) (Eq. 7), and with
                   their transposes, by the naive power sum; the
                   implicit row gather M[rows, :] (Section 3.2, option (ii)).
+- symbolic.py   : the DAG of product functions of Section 4 and the
+                  appendix (dense, sparse and diagonal leaves; sum, product,
+                  scalar multiple, power, transpose, row gather, column and
+                  row concatenation), evaluated as the definitions read.
 - isvd.py       : Algorithm 1 (randomized SVD of an implicit matrix) with
                   Householder QR or Cholesky orthonormalisation
                   (Algorithm 2), and the per-triplet residual.

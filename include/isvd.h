@@ -59,7 +59,8 @@ typedef enum {
 
 typedef enum {
   ISVD_FORM_NE = 0,
-  ISVD_FORM_FEATPROP = 1
+  ISVD_FORM_FEATPROP = 1,
+  ISVD_FORM_DAG = 2 /* an operator from isvd_dag_operator (not for isvd_create_operator) */
 } isvd_form;
 
 /* Sparse adjacency A (n x n) in CSR form, device memory, borrowed.
@@ -244,6 +245,72 @@ isvd_status isvd_gram(int64_t rows, int64_t m, int64_t p, isvd_precision precisi
  * The small Rayleigh-Ritz SVD of Algorithm 1 (its svd of B).  Enqueued only. */
 isvd_status isvd_small_svd(int64_t n, const double* A, double* Uo, double* s, double* Vo,
                            void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Symbolic design matrices (Section 4 and the appendix on symbolic
+ * representation): a DAG whose leaf nodes hold a matrix explicitly and whose
+ * symbolic nodes are functions of other nodes; a product with a block walks
+ * the DAG down to the leaves.  isvd_dag_operator turns any node into an
+ * operator for isvd_matmul_block, isvd_truncated_svd and
+ * isvd_operator_gather_rows.
+ *
+ * A DAG has one precision (ISVD_FP64 or ISVD_FP32): its dense leaves and
+ * every block it multiplies are of that type.  Node ids are returned in
+ * *id (>= 0).  Leaves borrow their device arrays (valid and unchanged while
+ * the DAG lives) except where copied is said.  The DAG must outlive every
+ * operator made from it.  Building nodes launches no GPU work except for
+ * isvd_dag_diag and isvd_dag_gather_rows (copies, synchronised).
+ *
+ * Evaluation (isvd_matmul_block on a DAG operator): products are flattened
+ * into chains of factors applied from the right (transposes pushed down to
+ * the leaves, scalars collected); a diagonal beside a sparse leaf is fused
+ * into its pass as a row or column scale; sums and concatenations
+ * accumulate their terms.  With lazy_cache != 0 the result of every chain
+ * suffix times the input block is kept for the duration of one product and
+ * reused (the appendix's cache keyed by the ordered list of factors
+ * multiplied onto the block), so t, t@t, t@t@t cost three passes, not six.
+ * Workspace (device blocks of the product's width) is owned by the
+ * operator and reused between calls.
+ * ------------------------------------------------------------------------ */
+
+typedef struct isvd_dag isvd_dag;
+
+isvd_status isvd_dag_create(isvd_precision precision, isvd_dag** out);
+/* Releases the DAG (NULL ignored); its operators must be destroyed first. */
+void isvd_dag_destroy(isvd_dag* dag);
+
+/* Sparse leaf (rows x cols CSR, device, borrowed; values NULL = all ones).
+ * Its transpose uses t_* (the CSR of the transpose, cols x rows) or, with
+ * symmetric != 0 (rows == cols and the matrix equals its transpose), the
+ * same arrays. */
+isvd_status isvd_dag_sparse(isvd_dag* dag, int64_t rows, int64_t cols, int64_t nnz, const int64_t* indptr,
+                            const int32_t* indices, const float* values, int symmetric, const int64_t* t_indptr,
+                            const int32_t* t_indices, const float* t_values, int64_t* id);
+/* Dense leaf: rows x cols row-major block X (ld ldx, the DAG's type,
+ * borrowed), cols <= 2048.  Products: X G by an MFMA tall GEMM, X^T Q by
+ * the FP64-MFMA Gram (cols + width <= 2048), rounded to the DAG's type. */
+isvd_status isvd_dag_dense(isvd_dag* dag, int64_t rows, int64_t cols, const void* X, int64_t ldx, int64_t* id);
+/* Diagonal leaf diag(d), d: n doubles (device, copied). */
+isvd_status isvd_dag_diag(isvd_dag* dag, int64_t n, const double* d, int64_t* id);
+/* sum_i w_i M_i over `count` nodes of one shape (ids, weights: host arrays;
+ * weights NULL = all ones).  A scalar multiple is a one-term sum. */
+isvd_status isvd_dag_sum(isvd_dag* dag, int count, const int64_t* ids, const double* weights, int64_t* id);
+/* M_1 M_2 ... M_count (ids: host array; inner dimensions must agree).  A
+ * power is a product of copies of one id. */
+isvd_status isvd_dag_product(isvd_dag* dag, int count, const int64_t* ids, int64_t* id);
+/* M^T. */
+isvd_status isvd_dag_transpose(isvd_dag* dag, int64_t node, int64_t* id);
+/* M[rows, :] (rows: nsub distinct device int64 indices, copied and checked,
+ * synchronised; ISVD_E_INVALID for one out of range or repeated). */
+isvd_status isvd_dag_gather_rows(isvd_dag* dag, int64_t node, const int64_t* rows, int64_t nsub, int64_t* id);
+/* [M_1, ..., M_count] side by side (equal row counts; ids host).  The
+ * transpose of a column concatenation stacks the parts' transposes. */
+isvd_status isvd_dag_concat_cols(isvd_dag* dag, int count, const int64_t* ids, int64_t* id);
+/* (rows, cols) of a node (host outputs). */
+isvd_status isvd_dag_shape(const isvd_dag* dag, int64_t node, int64_t* rows, int64_t* cols);
+/* An operator for node `root` (form ISVD_FORM_DAG).  Destroy it with
+ * isvd_destroy_operator before the DAG. */
+isvd_status isvd_dag_operator(isvd_dag* dag, int64_t root, int lazy_cache, isvd_operator** out);
 
 /* ---------------------------------------------------------------------------
  * Closed-form learners on a rank-k SVD (Section 3).  U (rows_u x k), V

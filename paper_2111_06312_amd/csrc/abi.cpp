@@ -4,6 +4,7 @@
 #include <mutex>
 #include <string>
 
+#include "dag.h"
 #include "learners.h"
 #include "operator.h"
 #include "spmm.h"
@@ -100,6 +101,230 @@ isvd_status isvd_operator_gather_rows(isvd_operator* op, const int64_t* rows, in
   return guarded([&]() -> isvd_status {
     ISVD_CHECK(op, ISVD_E_INVALID, "null operator");
     select_rows(op, rows, nsub, static_cast<hipStream_t>(stream));
+    return ISVD_OK;
+  });
+}
+
+// ------------------------------------------------------------------ symbolic DAG
+
+namespace {
+using isvd::DagKind;
+using isvd::DagNode;
+
+DagNode& dag_node(const isvd_dag* dag, int64_t id) {
+  ISVD_CHECK(dag && id >= 0 && id < static_cast<int64_t>(dag->nodes.size()), ISVD_E_INVALID, "dag: bad node id");
+  return *dag->nodes[static_cast<size_t>(id)];
+}
+
+int64_t dag_add(isvd_dag* dag, std::unique_ptr<DagNode> n) {
+  dag->nodes.push_back(std::move(n));
+  return static_cast<int64_t>(dag->nodes.size() - 1);
+}
+
+void dag_borrow_csr(isvd::Csr& c, int64_t rows, int64_t nnz, const int64_t* indptr, const int32_t* indices,
+                    const float* values) {
+  c.indptr = indptr;
+  c.indices = indices;
+  c.values = values;
+  c.nnz = nnz;
+  c.n_heavy = build_heavy_rows(rows, indptr, 256, c.heavy, nullptr);
+}
+}  // namespace
+
+isvd_status isvd_dag_create(isvd_precision precision, isvd_dag** out) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(out, ISVD_E_INVALID, "null output");
+    ISVD_CHECK(precision == ISVD_FP64 || precision == ISVD_FP32, ISVD_E_INVALID,
+               "symbolic matrices take FP64 or FP32 blocks");
+    auto* d = new isvd_dag();
+    d->prec = precision;
+    *out = d;
+    return ISVD_OK;
+  });
+}
+
+void isvd_dag_destroy(isvd_dag* dag) {
+  if (!dag) return;
+  (void)hipDeviceSynchronize();
+  delete dag;
+}
+
+isvd_status isvd_dag_sparse(isvd_dag* dag, int64_t rows, int64_t cols, int64_t nnz, const int64_t* indptr,
+                            const int32_t* indices, const float* values, int symmetric, const int64_t* t_indptr,
+                            const int32_t* t_indices, const float* t_values, int64_t* id) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(dag && id && rows >= 1 && cols >= 1 && nnz >= 0 && indptr && (nnz == 0 || indices), ISVD_E_INVALID,
+               "dag sparse: need a CSR");
+    ISVD_CHECK(rows < (int64_t(1) << 31) && cols < (int64_t(1) << 31), ISVD_E_INVALID,
+               "dag sparse: dimensions must fit int32 ids");
+    ISVD_CHECK(!symmetric || rows == cols, ISVD_E_INVALID, "dag sparse: a symmetric matrix is square");
+    ISVD_CHECK(symmetric || (t_indptr && (nnz == 0 || t_indices) && ((values == nullptr) == (t_values == nullptr))),
+               ISVD_E_INVALID, "dag sparse: a non-symmetric matrix needs the CSR of its transpose");
+    auto n = std::make_unique<DagNode>();
+    n->kind = DagKind::Sparse;
+    n->rows = rows;
+    n->cols = cols;
+    dag_borrow_csr(n->fwd, rows, nnz, indptr, indices, values);
+    if (symmetric)
+      dag_borrow_csr(n->bwd, rows, nnz, indptr, indices, values);
+    else
+      dag_borrow_csr(n->bwd, cols, nnz, t_indptr, t_indices, t_values);
+    ISVD_HIP(hipStreamSynchronize(nullptr));
+    *id = dag_add(dag, std::move(n));
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_dag_dense(isvd_dag* dag, int64_t rows, int64_t cols, const void* X, int64_t ldx, int64_t* id) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(dag && id && X && rows >= 1 && cols >= 1 && cols <= 2048 && ldx >= cols, ISVD_E_INVALID,
+               "dag dense: need rows >= 1, 1 <= cols <= 2048, ldx >= cols");
+    auto n = std::make_unique<DagNode>();
+    n->kind = DagKind::Dense;
+    n->rows = rows;
+    n->cols = cols;
+    n->X = X;
+    n->ldx = ldx;
+    *id = dag_add(dag, std::move(n));
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_dag_diag(isvd_dag* dag, int64_t nd, const double* d, int64_t* id) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(dag && id && d && nd >= 1, ISVD_E_INVALID, "dag diag: need n >= 1 values");
+    auto n = std::make_unique<DagNode>();
+    n->kind = DagKind::Diag;
+    n->rows = n->cols = nd;
+    n->d64.ensure(static_cast<size_t>(nd) * sizeof(double));
+    n->d32.ensure(static_cast<size_t>(nd) * sizeof(float));
+    ISVD_HIP(hipMemcpyAsync(n->d64.p, d, static_cast<size_t>(nd) * sizeof(double), hipMemcpyDeviceToDevice, nullptr));
+    launch_convert<float, double>(nd, 1, n->d64.as<double>(), 1, n->d32.as<float>(), 1, nullptr);
+    ISVD_HIP(hipStreamSynchronize(nullptr));
+    *id = dag_add(dag, std::move(n));
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_dag_sum(isvd_dag* dag, int count, const int64_t* ids, const double* weights, int64_t* id) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(dag && id && ids && count >= 1, ISVD_E_INVALID, "dag sum: need at least one term");
+    auto n = std::make_unique<DagNode>();
+    n->kind = DagKind::Sum;
+    const DagNode& first = dag_node(dag, ids[0]);
+    n->rows = first.rows;
+    n->cols = first.cols;
+    for (int i = 0; i < count; ++i) {
+      const DagNode& t = dag_node(dag, ids[i]);
+      ISVD_CHECK(t.rows == n->rows && t.cols == n->cols, ISVD_E_INVALID, "dag sum: terms of different shapes");
+      n->kids.push_back(ids[i]);
+      n->w.push_back(weights ? weights[i] : 1.0);
+    }
+    *id = dag_add(dag, std::move(n));
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_dag_product(isvd_dag* dag, int count, const int64_t* ids, int64_t* id) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(dag && id && ids && count >= 1, ISVD_E_INVALID, "dag product: need at least one factor");
+    auto n = std::make_unique<DagNode>();
+    n->kind = DagKind::Product;
+    for (int i = 0; i < count; ++i) {
+      const DagNode& f = dag_node(dag, ids[i]);
+      if (i > 0) ISVD_CHECK(dag_node(dag, ids[i - 1]).cols == f.rows, ISVD_E_INVALID, "dag product: inner dimensions differ");
+      n->kids.push_back(ids[i]);
+    }
+    n->rows = dag_node(dag, ids[0]).rows;
+    n->cols = dag_node(dag, ids[count - 1]).cols;
+    *id = dag_add(dag, std::move(n));
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_dag_transpose(isvd_dag* dag, int64_t node, int64_t* id) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(id, ISVD_E_INVALID, "null output");
+    const DagNode& k = dag_node(dag, node);
+    auto n = std::make_unique<DagNode>();
+    n->kind = DagKind::Transpose;
+    n->rows = k.cols;
+    n->cols = k.rows;
+    n->kids.push_back(node);
+    *id = dag_add(dag, std::move(n));
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_dag_gather_rows(isvd_dag* dag, int64_t node, const int64_t* rows, int64_t nsub, int64_t* id) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(id && rows, ISVD_E_INVALID, "null argument");
+    const DagNode& k = dag_node(dag, node);
+    ISVD_CHECK(nsub >= 1 && nsub <= k.rows, ISVD_E_INVALID, "dag gather: need 1 <= nsub <= rows");
+    auto n = std::make_unique<DagNode>();
+    n->kind = DagKind::Gather;
+    n->rows = nsub;
+    n->cols = k.cols;
+    n->nsub = nsub;
+    n->kids.push_back(node);
+    n->sel.ensure(static_cast<size_t>(nsub) * sizeof(int64_t));
+    n->pos.ensure(static_cast<size_t>(k.rows) * sizeof(int32_t));
+    DevBuf flag;
+    flag.ensure(sizeof(int));
+    ISVD_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), nullptr));
+    ISVD_HIP(hipMemcpyAsync(n->sel.p, rows, static_cast<size_t>(nsub) * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                            nullptr));
+    build_row_selection(k.rows, nsub, n->sel.as<int64_t>(), n->pos.as<int32_t>(), flag.as<int>(), nullptr);
+    int f = 0;
+    ISVD_HIP(hipMemcpyAsync(&f, flag.p, sizeof(int), hipMemcpyDeviceToHost, nullptr));
+    ISVD_HIP(hipStreamSynchronize(nullptr));
+    ISVD_CHECK(f == 0, ISVD_E_INVALID, (f & 1) ? "dag gather: index out of range" : "dag gather: repeated index");
+    *id = dag_add(dag, std::move(n));
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_dag_concat_cols(isvd_dag* dag, int count, const int64_t* ids, int64_t* id) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(dag && id && ids && count >= 1, ISVD_E_INVALID, "dag concat: need at least one part");
+    auto n = std::make_unique<DagNode>();
+    n->kind = DagKind::Concat;
+    n->rows = dag_node(dag, ids[0]).rows;
+    n->cols = 0;
+    for (int i = 0; i < count; ++i) {
+      const DagNode& p = dag_node(dag, ids[i]);
+      ISVD_CHECK(p.rows == n->rows, ISVD_E_INVALID, "dag concat: parts of different row counts");
+      n->kids.push_back(ids[i]);
+      n->cols += p.cols;
+    }
+    *id = dag_add(dag, std::move(n));
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_dag_shape(const isvd_dag* dag, int64_t node, int64_t* rows, int64_t* cols) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(rows && cols, ISVD_E_INVALID, "null output");
+    const DagNode& n = dag_node(dag, node);
+    *rows = n.rows;
+    *cols = n.cols;
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_dag_operator(isvd_dag* dag, int64_t root, int lazy_cache, isvd_operator** out) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(out, ISVD_E_INVALID, "null output");
+    *out = nullptr;
+    const DagNode& r = dag_node(dag, root);
+    auto* op = new isvd_operator();
+    op->form = ISVD_FORM_DAG;
+    op->prec = dag->prec;
+    op->n = r.rows;
+    op->rows = r.rows;
+    op->cols = r.cols;
+    op->dag_eval = make_dag_eval(dag, root, lazy_cache != 0);
+    *out = op;
     return ISVD_OK;
   });
 }

@@ -19,6 +19,8 @@
 //     M^T Q = [X^T P_0; ...; X^T P_L], P_0 = Q, P_j = Ah^T P_{j-1} : L passes, one X^T [P] Gram
 #include "operator.h"
 
+#include "dag.h"
+
 #include <algorithm>
 
 namespace isvd {
@@ -224,8 +226,17 @@ namespace {
 template <typename T>
 void apply_full(isvd_operator* op, bool transpose, const T* Y, int64_t ldy, int ncols, T* out, int64_t ldo,
                 hipStream_t stream, const double* colsum_y) {
-  if (op->form == ISVD_FORM_NE) apply_ne<T>(op, transpose, Y, ldy, ncols, out, ldo, stream, colsum_y);
-  else apply_featprop<T>(op, transpose, Y, ldy, ncols, out, ldo, stream);
+  if (op->form == ISVD_FORM_NE) {
+    apply_ne<T>(op, transpose, Y, ldy, ncols, out, ldo, stream, colsum_y);
+  } else if (op->form == ISVD_FORM_FEATPROP) {
+    apply_featprop<T>(op, transpose, Y, ldy, ncols, out, ldo, stream);
+  } else {
+    if constexpr (std::is_same<T, bf16>::value) {
+      throw Error{ISVD_E_UNSUPPORTED, "symbolic operators take FP64 or FP32 blocks"};
+    } else {
+      dag_apply<T>(*op->dag_eval, transpose, Y, ldy, ncols, out, ldo, stream);
+    }
+  }
 }
 }  // namespace
 

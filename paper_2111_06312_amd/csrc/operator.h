@@ -44,6 +44,8 @@ struct Csr {
   int64_t n_heavy = 0;
 };
 
+struct DagEval;
+
 }  // namespace isvd
 
 struct isvd_operator {
@@ -71,6 +73,7 @@ struct isvd_operator {
   isvd::DevBuf tmp[3];
   isvd::DevBuf colsum_part, svec, gram_work, side_c, side_b;
   std::shared_ptr<void> svd_cache;  // workspace of isvd_truncated_svd, kept between calls
+  std::shared_ptr<isvd::DagEval> dag_eval;  // symbolic form: the evaluator of its root node
   hipStream_t stream = nullptr;
 
   template <typename T>

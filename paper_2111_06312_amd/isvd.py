@@ -87,6 +87,19 @@ def load():
     lib.isvd_destroy_operator.restype = None
     lib.isvd_operator_shape.argtypes = [vp, ct.POINTER(i64), ct.POINTER(i64)]
     lib.isvd_operator_gather_rows.argtypes = [vp, vp, i64, vp]
+    lib.isvd_dag_create.argtypes = [st, ct.POINTER(vp)]
+    lib.isvd_dag_destroy.argtypes = [vp]
+    lib.isvd_dag_destroy.restype = None
+    lib.isvd_dag_sparse.argtypes = [vp, i64, i64, i64, vp, vp, vp, st, vp, vp, vp, ct.POINTER(i64)]
+    lib.isvd_dag_dense.argtypes = [vp, i64, i64, vp, i64, ct.POINTER(i64)]
+    lib.isvd_dag_diag.argtypes = [vp, i64, vp, ct.POINTER(i64)]
+    lib.isvd_dag_sum.argtypes = [vp, st, vp, vp, ct.POINTER(i64)]
+    lib.isvd_dag_product.argtypes = [vp, st, vp, ct.POINTER(i64)]
+    lib.isvd_dag_transpose.argtypes = [vp, i64, ct.POINTER(i64)]
+    lib.isvd_dag_gather_rows.argtypes = [vp, i64, vp, i64, ct.POINTER(i64)]
+    lib.isvd_dag_concat_cols.argtypes = [vp, st, vp, ct.POINTER(i64)]
+    lib.isvd_dag_shape.argtypes = [vp, i64, ct.POINTER(i64), ct.POINTER(i64)]
+    lib.isvd_dag_operator.argtypes = [vp, i64, st, ct.POINTER(vp)]
     lib.isvd_matmul_block.argtypes = [vp, st, vp, i64, i64, vp, i64, vp]
     lib.isvd_truncated_svd.argtypes = [vp, ct.POINTER(_SvdParams), vp, i64, vp, vp, i64, ct.POINTER(_SvdInfo), vp]
     lib.isvd_gaussian_block.argtypes = [i64, i64, ct.c_uint64, st, vp, i64, vp]
@@ -167,6 +180,7 @@ class Operator:
                           ldx=_ld(X), L=int(L))
         else:
             raise ValueError(form)
+        self.device = self._indptr.device
         handle = ct.c_void_p()
         _check(lib.isvd_create_operator(ct.byref(g), ct.byref(dsn), precision, _stream(), ct.byref(handle)))
         self.handle = handle
@@ -192,7 +206,7 @@ class Operator:
             if rows is None:
                 _check(_lib.isvd_operator_gather_rows(self.handle, None, 0, _stream()))
             else:
-                r = torch.as_tensor(rows, dtype=torch.int64, device=self._indptr.device).contiguous()
+                r = torch.as_tensor(rows, dtype=torch.int64, device=self.device).contiguous()
                 _check(_lib.isvd_operator_gather_rows(self.handle, _ptr(r), r.shape[0], _stream()))
         finally:
             nr, nc = ct.c_int64(), ct.c_int64()
@@ -215,7 +229,7 @@ class Operator:
         """(U, S, V, info) through isvd_truncated_svd."""
         r, c = self.shape
         out_dtype = torch.float32 if self.precision == BF16 else self.dtype
-        dev = self._indptr.device
+        dev = self.device
         U = torch.empty((r, k), dtype=out_dtype, device=dev)
         V = torch.empty((c, k), dtype=out_dtype, device=dev)
         S = torch.empty(k, dtype=torch.float64, device=dev)
@@ -232,6 +246,126 @@ class Operator:
         return U, S, V, SvdInfo(info.iterations, info.applies, info.bf16_iterations, info.residual_checks,
                                 info.used_fallback, info.residual, info.seconds, st, info.ritz_steps,
                                 info.jacobi_sweeps)
+
+
+class Dag:
+    """A symbolic matrix DAG (isvd_dag_*): leaves hold device arrays, nodes
+    combine them; `operator(node)` gives an Operator for products and the SVD.
+    Leaf arrays are kept alive by this object."""
+
+    def __init__(self, precision=FP32, device="cuda"):
+        lib = load()
+        assert precision in (FP32, FP64)
+        self.precision = precision
+        self.dtype = _DTYPE[precision]
+        self.device = torch.device(device)
+        self._keep = []
+        h = ct.c_void_p()
+        _check(lib.isvd_dag_create(precision, ct.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.isvd_dag_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _node(self, fn, *args):
+        out = ct.c_int64()
+        _check(fn(self.handle, *args, ct.byref(out)))
+        return DagNode(self, out.value)
+
+    def sparse(self, indptr, indices, shape, values=None, symmetric=True, t_indptr=None, t_indices=None,
+               t_values=None):
+        """CSR leaf (host or device arrays; copied to the device and kept)."""
+        def dev(a, dt):
+            return None if a is None else torch.as_tensor(np.asarray(a) if not torch.is_tensor(a) else a,
+                                                          dtype=dt, device=self.device).contiguous()
+        arrs = [dev(indptr, torch.int64), dev(indices, torch.int32), dev(values, torch.float32),
+                dev(t_indptr, torch.int64), dev(t_indices, torch.int32), dev(t_values, torch.float32)]
+        for i in (1, 4):
+            if arrs[i] is not None and arrs[i].numel() == 0:
+                arrs[i] = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self._keep += [a for a in arrs if a is not None]
+        nnz = int(arrs[0][-1].item())
+        return self._node(_lib.isvd_dag_sparse, shape[0], shape[1], nnz, _ptr(arrs[0]), _ptr(arrs[1]),
+                          _ptr(arrs[2]), 1 if symmetric else 0, _ptr(arrs[3]), _ptr(arrs[4]), _ptr(arrs[5]))
+
+    def dense(self, X):
+        assert X.dtype == self.dtype and X.is_cuda
+        self._keep.append(X)
+        return self._node(_lib.isvd_dag_dense, X.shape[0], X.shape[1], _ptr(X), _ld(X))
+
+    def diag(self, d):
+        t = torch.as_tensor(d, dtype=torch.float64, device=self.device).contiguous()
+        return self._node(_lib.isvd_dag_diag, t.shape[0], _ptr(t))
+
+    def sum(self, nodes, weights=None):
+        ids = (ct.c_int64 * len(nodes))(*[n.id for n in nodes])
+        w = None if weights is None else (ct.c_double * len(nodes))(*[float(x) for x in weights])
+        return self._node(_lib.isvd_dag_sum, len(nodes), ids, w)
+
+    def product(self, nodes):
+        ids = (ct.c_int64 * len(nodes))(*[n.id for n in nodes])
+        return self._node(_lib.isvd_dag_product, len(nodes), ids)
+
+    def concat_cols(self, nodes):
+        ids = (ct.c_int64 * len(nodes))(*[n.id for n in nodes])
+        return self._node(_lib.isvd_dag_concat_cols, len(nodes), ids)
+
+    def operator(self, node, lazy_cache=True):
+        h = ct.c_void_p()
+        _check(_lib.isvd_dag_operator(self.handle, node.id, 1 if lazy_cache else 0, ct.byref(h)))
+        op = Operator.__new__(Operator)
+        op.precision = self.precision
+        op.dtype = self.dtype
+        op.device = self.device
+        op.handle = h
+        op._dag = self
+        op.shape = node.shape
+        op.n = node.shape[0]
+        return op
+
+
+class DagNode:
+    """A node of a Dag; Python operators build new nodes (one C call each)."""
+
+    def __init__(self, dag, nid):
+        self.dag = dag
+        self.id = nid
+        r, c = ct.c_int64(), ct.c_int64()
+        _check(_lib.isvd_dag_shape(dag.handle, nid, ct.byref(r), ct.byref(c)))
+        self.shape = (r.value, c.value)
+
+    def __add__(self, other):
+        return self.dag.sum([self, other])
+
+    def __sub__(self, other):
+        return self.dag.sum([self, other], [1.0, -1.0])
+
+    def __mul__(self, alpha):
+        return self.dag.sum([self], [float(alpha)])
+
+    __rmul__ = __mul__
+
+    def __matmul__(self, other):
+        return self.dag.product([self, other])
+
+    def __pow__(self, p):
+        return self.dag.product([self] * int(p))
+
+    @property
+    def T(self):
+        return self.dag._node(_lib.isvd_dag_transpose, self.id)
+
+    def gather_rows(self, rows):
+        r = torch.as_tensor(rows, dtype=torch.int64, device=self.dag.device).contiguous()
+        return self.dag._node(_lib.isvd_dag_gather_rows, self.id, _ptr(r), r.shape[0])
 
 
 def profile_spmm(on=True):

@@ -55,6 +55,10 @@ def parse():
                     help="time the closed-form learners instead: Eq. 5 embeddings and pair scores on the "
                          "rank-128 SVD of the n = 200,000 NE workload, and the Eq. 8 least-norm model on the "
                          "rank-64 SVD of the n = 170,000 feature-propagation workload (one JSON line)")
+    ap.add_argument("--dag", action="store_true",
+                    help="time the symbolic form instead: the NE matrix of the n = 200,000 workload built as "
+                         "Fig. 1 builds it (leaves A, D^-1 and a ones column), products and one iSVD step, "
+                         "with and without the lazy cache, beside the fused operator (one JSON line)")
     ap.add_argument("--pairs", type=int, default=2_000_000)
     ap.add_argument("--label-frac", type=float, default=0.5)
     return ap.parse_args()
@@ -76,6 +80,78 @@ def _timed(lib, torch, name, fn, reps):
     lib.profile_spmm(False)
     assert rec[2] == reps, rec
     return t_call / reps, rec[0] / 1e3 / reps, rec[1] / reps
+
+
+def dag_bench(args, lib, torch, np):
+    """Symbolic form (Section 4) on the n = 200,000 NE workload.
+
+    M = sum_j (1/10) t^j - 0.1 (1 1^T - A), t = D^-1 A, built from three
+    leaves as in Fig. 1.  Per product pair (M Y and M^T Y, l = 144, FP32):
+    device time (library HIP events over the sparse passes plus the host
+    clock of the whole pair) and sparse passes, for the fused operator and
+    for the DAG operator with and without the lazy cache; then one iSVD step
+    to rho <= 1e-4 through the DAG with the cache."""
+    import scipy.sparse as sp
+    from synth import CONFIGS
+    from synth.configs import make_graph
+
+    cfg = CONFIGS["c2"]
+    g = make_graph(cfg)
+    a = sp.csr_matrix((np.ones(len(g.indices)), g.indices, g.indptr), shape=(g.n, g.n))
+    deg = np.diff(a.indptr).astype(np.float64)
+    dag = lib.Dag(lib.FP32)
+    A = dag.sparse(a.indptr, a.indices, a.shape)
+    t = dag.diag(np.where(deg > 0, 1.0 / np.maximum(deg, 1.0), 0.0)) @ A
+    one = dag.dense(torch.ones((g.n, 1), dtype=torch.float32, device="cuda"))
+    m = dag.sum([t ** j for j in range(1, cfg.K + 1)], cfg.coeffs) - cfg.lam * (one @ one.T - A)
+    ops = {"fused": lib.Operator(g, form="ne", coeffs=cfg.coeffs, lam=cfg.lam, precision=lib.FP32),
+           "dag_lazy_cache": dag.operator(m, lazy_cache=True),
+           "dag_no_cache": dag.operator(m, lazy_cache=False)}
+    y = lib.gaussian_block(g.n, cfg.l, seed=1)
+    res = {}
+    for name, op in ops.items():
+        for _ in range(args.warmup):
+            op.matmul(op.matmul(y), transpose=True)
+        torch.cuda.synchronize()
+        lib.profile_spmm(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            op.matmul(op.matmul(y), transpose=True)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        ms, gb, _, launches = lib.profile_spmm_read()
+        lib.profile_spmm(False)
+        res[name] = {"pair_ms": round(1e3 * wall, 3), "passes_per_pair": launches // args.steps,
+                     "spmm_ms_per_pair": round(ms / args.steps, 3),
+                     "spmm_gbps": round(gb / (ms / 1e3) / 1e9, 1) if ms > 0 else None}
+        print(f"[bench] {name}: {res[name]}", file=sys.stderr, flush=True)
+    svd = {}
+    for name in ("fused", "dag_lazy_cache"):
+        op = ops[name]
+        op.truncated_svd(cfg.k, cfg.p, tol=1e-4, max_iter=2000, seed=1000)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, info = op.truncated_svd(cfg.k, cfg.p, tol=1e-4, max_iter=2000, seed=0)
+        torch.cuda.synchronize()
+        svd[name] = {"s": round(time.perf_counter() - t0, 4), "iterations": info.iterations,
+                     "residual": info.residual}
+        print(f"[bench] svd {name}: {svd[name]}", file=sys.stderr, flush=True)
+    for op in ops.values():
+        op.close()
+    dag.close()
+    line = {
+        "metric": "symbolic-form product pair and iSVD step time vs the fused form (Section 4)",
+        "value": svd["dag_lazy_cache"]["s"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "higher_is_better": False, "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name + "_fig1_dag", "n": g.n, "nnz": int(g.nnz), "K": cfg.K, "l": cfg.l,
+                   "products": res, "svd": svd,
+                   "lazy_cache_speedup": round(res["dag_no_cache"]["pair_ms"] / res["dag_lazy_cache"]["pair_ms"], 2)},
+        "roofline": {"bound": "hbm", "kernel": "spmm_pass_kernel (in the DAG with the cache)",
+                     "achieved": res["dag_lazy_cache"]["spmm_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(res["dag_lazy_cache"]["spmm_gbps"] / HBM_PEAK_GBPS, 4), "traffic": None},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def learners_bench(args, lib, torch, np):
@@ -205,6 +281,9 @@ def main():
         del src, dst
     if args.learners:
         learners_bench(args, lib, torch, np)
+        return
+    if args.dag:
+        dag_bench(args, lib, torch, np)
         return
     cfg = CONFIGS[args.config]
     prec_name = args.precision or ("bf16" if cfg.precision == "bf16" else "fp32")

@@ -9,7 +9,8 @@
 // below it (a part of a column concatenation), or a sum / concatenation whose
 // terms are chains of their own, continued by the rest of the enclosing
 // chain.  A diagonal next to a sparse leaf becomes the row or column scale
-// of that leaf's sparse pass.  With the lazy cache, the result of every
+// of that leaf's sparse pass (groups formed from the right end of the chain,
+// so that equal suffixes are grouped alike).  With the lazy cache, the result of every
 // chain suffix times G is kept until the product is done and looked up by
 // the ordered list of its factors (the appendix's cache key), so shared
 // suffixes (t, t@t, t@t@t; the terms of a sum that end alike) are
@@ -162,17 +163,44 @@ class Evaluator {
     return i < c.size() && c[i].kind == Atom::Node && node_of(ev_, c[i].node).kind == k;
   }
 
+  // Length of the factor group that starts at `pos`.  Groups are formed from
+  // the right end of the chain, so a suffix is grouped the same way whatever
+  // precedes it and cached suffix results are found again: a sparse leaf
+  // takes the diagonal on its left as its row scale; a diagonal with a
+  // sparse leaf on its left becomes that leaf's column scale, and the group
+  // also takes a diagonal further left as row scale unless that one sits
+  // right of another sparse leaf (D A D A: (D A)(D A); A D A D: (A D)(A D);
+  // R A R R A R: (R A R)(R A R)).  Everything else is a group of one.
+  size_t unit_length(const Chain& c, size_t pos) const {
+    std::vector<size_t> len(c.size(), 0);
+    auto diag = [&](std::ptrdiff_t i) { return i >= 0 && is_kind(c, static_cast<size_t>(i), DagKind::Diag); };
+    auto sparse = [&](std::ptrdiff_t i) { return i >= 0 && is_kind(c, static_cast<size_t>(i), DagKind::Sparse); };
+    std::ptrdiff_t i = static_cast<std::ptrdiff_t>(c.size()) - 1;
+    while (i >= 0) {
+      std::ptrdiff_t st = i;
+      if (diag(i) && sparse(i - 1)) {
+        st = i - 1;
+        if (diag(st - 1) && !sparse(st - 2)) st -= 1;
+      } else if (sparse(i)) {
+        if (diag(i - 1)) st = i - 1;
+      }
+      len[static_cast<size_t>(st)] = static_cast<size_t>(i - st + 1);
+      i = st - 1;
+    }
+    ISVD_CHECK(len[pos] > 0, ISVD_E_INVALID, "dag: evaluation inside a factor group");
+    return len[pos];
+  }
+
   const C* diag_vals(const DagNode& n) const {
     if constexpr (sizeof(C) == 8) return n.d64.as<double>();
     else return n.d32.as<float>();
   }
 
-  // One sparse pass: out = [diag(r)] A [diag(g)] X
-  View<T> sparse_pass(const DagNode& a, bool t, const DagNode* rs, const DagNode* cs, const View<T>& X) {
+  // The pass acc = A [diag(g)] X; the caller sets the epilogue (out, scales).
+  SpmmPass pass_for(const DagNode& a, bool t, const DagNode* cs, const View<T>& X) const {
     const Csr& csr = t ? a.bwd : a.fwd;
-    View<T> out = acquire(t ? a.cols : a.rows);
     SpmmPass p;
-    p.n_rows = out.rows;
+    p.n_rows = t ? a.cols : a.rows;
     p.nnz = csr.nnz;
     p.indptr = csr.indptr;
     p.indices = csr.indices;
@@ -188,6 +216,13 @@ class Evaluator {
       p.cs_a = 1.0;
       p.cs_b = 0.0;
     }
+    return p;
+  }
+
+  // One sparse pass: out = [diag(r)] A [diag(g)] X
+  View<T> sparse_pass(const DagNode& a, bool t, const DagNode* rs, const DagNode* cs, const View<T>& X) {
+    SpmmPass p = pass_for(a, t, cs, X);
+    View<T> out = acquire(p.n_rows);
     if (rs) {
       p.rowscale = diag_vals(*rs);
       p.a0 = 0.0;
@@ -197,6 +232,112 @@ class Evaluator {
     p.ld_out = out.ld;
     launch_spmm_pass<T>(p, s_);
     return out;
+  }
+
+  struct Group {
+    const DagNode* rs = nullptr;
+    const DagNode* cs = nullptr;
+    const Atom* sparse = nullptr;
+    size_t len = 1;
+  };
+
+  // The factor group at `pos` if it is a sparse pass (a sparse leaf with its scales).
+  bool sparse_group(const Chain& c, size_t pos, Group& g) const {
+    const Atom& a = c[pos];
+    if (a.kind != Atom::Node) return false;
+    const DagKind k = node_of(ev_, a.node).kind;
+    if (k != DagKind::Sparse && k != DagKind::Diag) return false;
+    g.len = unit_length(c, pos);
+    if (k == DagKind::Diag && g.len == 1) return false;
+    size_t i = pos;
+    if (is_kind(c, i, DagKind::Diag)) g.rs = &node_of(ev_, c[i++].node);
+    g.sparse = &c[i++];
+    if (i < pos + g.len) g.cs = &node_of(ev_, c[i].node);
+    return true;
+  }
+
+  // out (+)= coef * (chain times the input).  When the chain starts with a
+  // sparse pass, that pass adds into `out` in its epilogue and, with the
+  // cache on, also writes the chain's own result for later lookups (second
+  // output), so no separate accumulation pass is needed.
+  void accumulate(const Chain& c, double coef, const View<T>& out, bool first) {
+    Chain key;
+    if (ev_.cache_on) {
+      key = c;
+      auto it = cache_.find(key);
+      if (it != cache_.end()) {
+        launch_axpby<T>(out.rows, l_, coef, it->second.p, it->second.ld, first ? 0.0 : 1.0, out.p, out.ld, s_);
+        return;
+      }
+    }
+    Group g;
+    if (!sparse_group(c, 0, g)) {
+      View<T> Y = eval(c, 0);
+      launch_axpby<T>(out.rows, l_, coef, Y.p, Y.ld, first ? 0.0 : 1.0, out.p, out.ld, s_);
+      release(Y);
+      return;
+    }
+    View<T> X = eval(c, g.len);
+    SpmmPass p = pass_for(node_of(ev_, g.sparse->node), g.sparse->t, g.cs, X);
+    if (g.rs) {
+      p.rowscale = diag_vals(*g.rs);
+      p.a0 = 0.0;
+      p.a1 = coef;
+    } else {
+      p.a0 = coef;
+      p.a1 = 0.0;
+    }
+    if (!first) {
+      p.add = out.p;  // row-local read before the write of the same row
+      p.ld_add = out.ld;
+      p.b0 = 1.0;
+    }
+    p.out = out.p;
+    p.ld_out = out.ld;
+    if (ev_.cache_on) {
+      View<T> held = acquire(p.n_rows);
+      p.out2 = held.p;
+      p.ld_out2 = held.ld;
+      p.c0 = g.rs ? 0.0 : 1.0;
+      p.c1 = g.rs ? 1.0 : 0.0;
+      held.owner = -1;
+      cache_.emplace(std::move(key), held);
+    }
+    launch_spmm_pass<T>(p, s_);
+    release(X);
+  }
+
+ public:
+  // out = coef * (chain times the input), accumulating a leading sum or
+  // column concatenation straight into `out`.
+  void eval_into(const Chain& chain, double coef, const View<T>& out) {
+    const Atom& a = chain[0];
+    if (chain.size() == 1 && a.kind == Atom::Node) {
+      const DagNode& n = node_of(ev_, a.node);
+      if (n.kind == DagKind::Sum || (n.kind == DagKind::Concat && !a.t)) {
+        sum_terms(chain, 0, coef, out);
+        return;
+      }
+    }
+    View<T> v = eval(chain, 0);
+    launch_axpby<T>(out.rows, l_, coef, v.p, v.ld, 0.0, out.p, out.ld, s_);
+    release(v);
+  }
+
+ private:
+  // The terms of the sum or column concatenation at chain[pos], each
+  // continued by the rest of the chain, accumulated into out with `scale`.
+  void sum_terms(const Chain& chain, size_t pos, double scale, const View<T>& out) {
+    const Atom& a = chain[pos];
+    const DagNode& n = node_of(ev_, a.node);
+    for (size_t k = 0; k < n.kids.size(); ++k) {
+      Chain c;
+      double coef = scale * (n.kind == DagKind::Sum ? n.w[k] : 1.0);
+      flatten(ev_, n.kids[k], a.t, c, coef);
+      if (n.kind == DagKind::Concat) c.push_back({Atom::Slice, a.node, false, static_cast<int>(k)});
+      c.insert(c.end(), chain.begin() + static_cast<std::ptrdiff_t>(pos) + 1, chain.end());
+      accumulate(c, coef, out, k == 0);
+    }
   }
 
   View<T> compute(const Chain& chain, size_t pos) {
@@ -223,35 +364,25 @@ class Evaluator {
       return out;
     }
     switch (n.kind) {
-      case DagKind::Sparse: {
-        const DagNode* cs = nullptr;
-        size_t next = pos + 1;
-        if (is_kind(chain, next, DagKind::Diag)) {
-          cs = &node_of(ev_, chain[next].node);
-          ++next;
-        }
-        View<T> X = eval(chain, next);
-        View<T> out = sparse_pass(n, a.t, nullptr, cs, X);
-        release(X);
-        return out;
-      }
+      case DagKind::Sparse:
       case DagKind::Diag: {
-        if (is_kind(chain, pos + 1, DagKind::Sparse)) {
-          const Atom& sa = chain[pos + 1];
-          const DagNode* cs = nullptr;
-          size_t next = pos + 2;
-          if (is_kind(chain, next, DagKind::Diag)) {
-            cs = &node_of(ev_, chain[next].node);
-            ++next;
-          }
-          View<T> X = eval(chain, next);
-          View<T> out = sparse_pass(node_of(ev_, sa.node), sa.t, &n, cs, X);
+        // the pass unit starting here (grouped from the right end of the chain)
+        const size_t len = unit_length(chain, pos);
+        size_t i = pos;
+        const DagNode* rs = nullptr;
+        const DagNode* cs = nullptr;
+        if (len == 1 && n.kind == DagKind::Diag) {
+          View<T> X = eval(chain, pos + 1);
+          View<T> out = acquire(n.rows);
+          launch_diag_scale<T>(n.rows, l_, n.d64.as<double>(), X.p, X.ld, out.p, out.ld, s_);
           release(X);
           return out;
         }
-        View<T> X = eval(chain, pos + 1);
-        View<T> out = acquire(n.rows);
-        launch_diag_scale<T>(n.rows, l_, n.d64.as<double>(), X.p, X.ld, out.p, out.ld, s_);
+        if (is_kind(chain, i, DagKind::Diag)) rs = &node_of(ev_, chain[i++].node);
+        const Atom& sa = chain[i++];
+        if (i < pos + len) cs = &node_of(ev_, chain[i++].node);
+        View<T> X = eval(chain, pos + len);
+        View<T> out = sparse_pass(node_of(ev_, sa.node), sa.t, rs, cs, X);
         release(X);
         return out;
       }
@@ -277,35 +408,26 @@ class Evaluator {
       }
       case DagKind::Sum: {
         View<T> out = acquire(out_rows(ev_, a));
-        for (size_t k = 0; k < n.kids.size(); ++k) {
-          Chain c;
-          double coef = n.w[k];
-          flatten(ev_, n.kids[k], a.t, c, coef);
-          c.insert(c.end(), chain.begin() + static_cast<std::ptrdiff_t>(pos) + 1, chain.end());
-          View<T> Y = eval(c, 0);
-          launch_axpby<T>(out.rows, l_, coef, Y.p, Y.ld, k == 0 ? 0.0 : 1.0, out.p, out.ld, s_);
-          release(Y);
-        }
+        sum_terms(chain, pos, 1.0, out);
         return out;
       }
       case DagKind::Concat: {
         View<T> out = acquire(out_rows(ev_, a));
+        if (!a.t) {
+          // [M_1 .. M_m] X = sum_k M_k X_k
+          sum_terms(chain, pos, 1.0, out);
+          return out;
+        }
+        // [M_1 .. M_m]^T X stacks M_k^T X
         int64_t off = 0;
         for (size_t k = 0; k < n.kids.size(); ++k) {
           Chain c;
           double coef = 1.0;
-          flatten(ev_, n.kids[k], a.t, c, coef);
-          if (!a.t) c.push_back({Atom::Slice, a.node, false, static_cast<int>(k)});
+          flatten(ev_, n.kids[k], true, c, coef);
           c.insert(c.end(), chain.begin() + static_cast<std::ptrdiff_t>(pos) + 1, chain.end());
           View<T> Y = eval(c, 0);
-          if (!a.t) {
-            // [M_1 .. M_m] X = sum_k M_k X_k
-            launch_axpby<T>(out.rows, l_, coef, Y.p, Y.ld, k == 0 ? 0.0 : 1.0, out.p, out.ld, s_);
-          } else {
-            // [M_1 .. M_m]^T X stacks M_k^T X
-            launch_axpby<T>(Y.rows, l_, coef, Y.p, Y.ld, 0.0, out.p + off * out.ld, out.ld, s_);
-            off += Y.rows;
-          }
+          launch_axpby<T>(Y.rows, l_, coef, Y.p, Y.ld, 0.0, out.p + off * out.ld, out.ld, s_);
+          off += Y.rows;
           release(Y);
         }
         return out;
@@ -344,9 +466,7 @@ void dag_apply(DagEval& ev, bool transpose, const T* Y, int64_t ldy, int ncols, 
   double coef = 1.0;
   flatten(ev, ev.root, transpose, chain, coef);
   Evaluator<T> e(ev, Y, ldy, transpose ? r.rows : r.cols, ncols, stream);
-  View<T> v = e.eval(chain, 0);
-  launch_axpby<T>(transpose ? r.cols : r.rows, ncols, coef, v.p, v.ld, 0.0, out, ldo, stream);
-  e.release(v);
+  e.eval_into(chain, coef, View<T>{out, ldo, transpose ? r.cols : r.rows, -1});
 }
 template void dag_apply<float>(DagEval&, bool, const float*, int64_t, int, float*, int64_t, hipStream_t);
 template void dag_apply<double>(DagEval&, bool, const double*, int64_t, int, double*, int64_t, hipStream_t);

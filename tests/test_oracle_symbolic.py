@@ -93,3 +93,30 @@ def test_shape_mismatch_is_refused():
         ProductPF([DensePF(np.ones((3, 4))), DensePF(np.ones((3, 4)))])
     with pytest.raises(AssertionError):
         SumPF([DensePF(np.ones((3, 4))), DensePF(np.ones((4, 3)))])
+
+
+def test_label_reuse_operator_has_a_zero_diagonal():
+    # Section 5.3 (label re-use): A_hat - (D + I)^-1 zeroes the diagonal of A_hat,
+    # so row i of (A_hat - (D+I)^-1) Y_train never sees label i
+    g = sbm_graph(80, 3, 0.1, 0.02, seed=9)
+    a = adjacency(g.n, g.indptr, g.indices)
+    dg = degrees(a)
+    b = SparsePF(sym_normalized(a)) - DiagPF(1.0 / (dg + 1.0))
+    dense = b.dense()
+    assert np.abs(np.diag(dense)).max() < 1e-15
+    y = np.eye(g.n)[:, :5]
+    assert np.allclose(b.dot(y)[np.arange(5), np.arange(5)], 0.0, atol=1e-15)
+    # off the diagonal it is A_hat itself
+    off = ~np.eye(g.n, dtype=bool)
+    assert np.allclose(dense[off], sym_normalized(a).toarray()[off], atol=1e-15)
+
+
+def test_symmetric_ne_variant_is_symmetric():
+    # replacing T by A_hat (Section 3.1) gives a symmetric M on an undirected graph
+    g = sbm_graph(60, 3, 0.15, 0.02, seed=10)
+    a = adjacency(g.n, g.indptr, g.indices)
+    ah = SparsePF(sym_normalized(a))
+    one = DensePF(np.ones((g.n, 1)))
+    m = SumPF([ah ** j for j in (1, 2, 3)], [0.5, 0.3, 0.2]) - 0.05 * (one @ one.T - SparsePF(a))
+    dense = m.dense()
+    assert np.allclose(dense, dense.T, atol=1e-14)

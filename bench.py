@@ -59,6 +59,10 @@ def parse():
                     help="time the symbolic form instead: the NE matrix of the n = 200,000 workload built as "
                          "Fig. 1 builds it (leaves A, D^-1 and a ones column), products and one iSVD step, "
                          "with and without the lazy cache, beside the fused operator (one JSON line)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="Fig. 3-style ablation on the n = 200,000 NE workload: iSVD time to rho <= 1e-4 for "
+                         "{Householder QR, Cholesky QR, CholeskyQR2 everywhere} x {fused form, DAG with the lazy "
+                         "cache, DAG without it} (one JSON line)")
     ap.add_argument("--pairs", type=int, default=2_000_000)
     ap.add_argument("--label-frac", type=float, default=0.5)
     return ap.parse_args()
@@ -150,6 +154,56 @@ def dag_bench(args, lib, torch, np):
         "roofline": {"bound": "hbm", "kernel": "spmm_pass_kernel (in the DAG with the cache)",
                      "achieved": res["dag_lazy_cache"]["spmm_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(res["dag_lazy_cache"]["spmm_gbps"] / HBM_PEAK_GBPS, 4), "traffic": None},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def ablation_bench(args, lib, torch, np):
+    """Orthonormaliser x product evaluation, one iSVD each to rho <= 1e-4
+    (after a one-iteration warm-up of the same configuration), on the
+    n = 200,000 NE workload built both ways (fused operator; Fig. 1 DAG)."""
+    import scipy.sparse as sp
+    from synth import CONFIGS
+    from synth.configs import make_graph
+
+    cfg = CONFIGS["c2"]
+    g = make_graph(cfg)
+    a = sp.csr_matrix((np.ones(len(g.indices)), g.indices, g.indptr), shape=(g.n, g.n))
+    deg = np.diff(a.indptr).astype(np.float64)
+    dag = lib.Dag(lib.FP32)
+    A = dag.sparse(a.indptr, a.indices, a.shape)
+    t = dag.diag(np.where(deg > 0, 1.0 / np.maximum(deg, 1.0), 0.0)) @ A
+    one = dag.dense(torch.ones((g.n, 1), dtype=torch.float32, device="cuda"))
+    m = dag.sum([t ** j for j in range(1, cfg.K + 1)], cfg.coeffs) - cfg.lam * (one @ one.T - A)
+    ops = {"fused": lib.Operator(g, form="ne", coeffs=cfg.coeffs, lam=cfg.lam, precision=lib.FP32),
+           "dag_lazy_cache": dag.operator(m, lazy_cache=True),
+           "dag_no_cache": dag.operator(m, lazy_cache=False)}
+    orths = {"householder_qr": dict(orth_method=1), "cholesky_qr": dict(orth_method=0),
+             "cholesky_qr2": dict(orth_method=0, orth_passes=2)}
+    res = {}
+    for pname, op in ops.items():
+        for oname, kw in orths.items():
+            op.truncated_svd(cfg.k, cfg.p, q=1, seed=1000, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, _, info = op.truncated_svd(cfg.k, cfg.p, tol=1e-4, max_iter=2000, seed=0,
+                                             allow_not_converged=True, **kw)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            res[f"{pname}/{oname}"] = {"s": round(sec, 3), "iterations": info.iterations,
+                                       "residual": info.residual, "status": info.status}
+            print(f"[bench] {pname} / {oname}: {sec:.3f} s, {info.iterations} iterations, "
+                  f"rho {info.residual:.2e}", file=sys.stderr, flush=True)
+    for op in ops.values():
+        op.close()
+    dag.close()
+    base = res["dag_no_cache/householder_qr"]["s"]
+    line = {
+        "metric": "iSVD time to rel. residual 1e-4 by orthonormaliser and product evaluation (Fig. 3 ablation)",
+        "value": res["fused/cholesky_qr"]["s"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "higher_is_better": False, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": cfg.name + "_ablation", "n": g.n, "k": cfg.k, "p": cfg.p, "runs": res,
+                   "ratio_to_no_cache_householder": {k: round(v["s"] / base, 3) for k, v in res.items()}},
     }
     print(json.dumps(line), flush=True)
 
@@ -284,6 +338,9 @@ def main():
         return
     if args.dag:
         dag_bench(args, lib, torch, np)
+        return
+    if args.ablation:
+        ablation_bench(args, lib, torch, np)
         return
     cfg = CONFIGS[args.config]
     prec_name = args.precision or ("bf16" if cfg.precision == "bf16" else "fp32")

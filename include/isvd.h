@@ -186,6 +186,8 @@ typedef struct {
   int orth_passes;       /* 2: CholeskyQR2 in every iteration; otherwise one Cholesky pass (Algorithm 2)
                             in iterations whose bases only feed the next product, CholeskyQR2 before
                             every Rayleigh-Ritz step */
+  int orth_method;       /* 0: Cholesky QR as above; 1: Householder QR in every orthonormalisation
+                            (Algorithm 2's QR; one pass, orth_passes ignored; a slower baseline) */
 } isvd_svd_params;
 
 typedef struct {
@@ -237,6 +239,14 @@ isvd_status isvd_orthonormalize(int64_t rows, int64_t cols, isvd_precision preci
 /* C = A^T B, A rows x m, B rows x p (same precision, leading dimensions lda,
  * ldb, m + p <= 2048), C m x p FP64 row-major (ldc), products formed exactly
  * and summed in FP64 in a fixed order.  Synchronises the stream. */
+/* Householder QR of Y (rows x cols, in place: Y <- Q; R_out optional, as for
+ * isvd_orthonormalize but R's diagonal may be negative), Algorithm 2's QR
+ * orthonormaliser: unblocked, two passes over the trailing block per column
+ * and per reflector, FP64 dot products.  1 <= cols <= min(rows, 1024).
+ * Allocates a rows x cols block of workspace per call. */
+isvd_status isvd_orthonormalize_householder(int64_t rows, int64_t cols, isvd_precision precision, void* Y,
+                                            int64_t ldy, double* R_out, void* stream);
+
 isvd_status isvd_gram(int64_t rows, int64_t m, int64_t p, isvd_precision precision, const void* A,
                       int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc, void* stream);
 

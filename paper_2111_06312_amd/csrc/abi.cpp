@@ -14,7 +14,8 @@ namespace isvd {
 isvd_status truncated_svd(isvd_operator* op, const isvd_svd_params* prm, void* U, int64_t ldu, double* S,
                           void* V, int64_t ldv, isvd_svd_info* info, hipStream_t stream);
 template <typename T>
-void orthonormalize_block(int64_t rows, int cols, T* Y, int64_t ld, double* Rout, hipStream_t stream);
+void orthonormalize_block(int64_t rows, int cols, T* Y, int64_t ld, double* Rout, hipStream_t stream,
+                          bool householder);
 
 namespace {
 thread_local std::string g_last_error;
@@ -384,9 +385,26 @@ isvd_status isvd_orthonormalize(int64_t rows, int64_t cols, isvd_precision preci
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int c = static_cast<int>(cols);
     switch (precision) {
-      case ISVD_FP64: orthonormalize_block<double>(rows, c, static_cast<double*>(Y), ldy, R_out, s); break;
-      case ISVD_FP32: orthonormalize_block<float>(rows, c, static_cast<float*>(Y), ldy, R_out, s); break;
-      case ISVD_BF16: orthonormalize_block<bf16>(rows, c, static_cast<bf16*>(Y), ldy, R_out, s); break;
+      case ISVD_FP64: orthonormalize_block<double>(rows, c, static_cast<double*>(Y), ldy, R_out, s, false); break;
+      case ISVD_FP32: orthonormalize_block<float>(rows, c, static_cast<float*>(Y), ldy, R_out, s, false); break;
+      case ISVD_BF16: orthonormalize_block<bf16>(rows, c, static_cast<bf16*>(Y), ldy, R_out, s, false); break;
+      default: throw Error{ISVD_E_INVALID, "bad precision"};
+    }
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_orthonormalize_householder(int64_t rows, int64_t cols, isvd_precision precision, void* Y,
+                                            int64_t ldy, double* R_out, void* stream) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(Y && cols >= 1 && cols <= 1024 && rows >= cols && ldy >= cols, ISVD_E_INVALID,
+               "need 1 <= cols <= min(rows, 1024) and ldy >= cols");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int c = static_cast<int>(cols);
+    switch (precision) {
+      case ISVD_FP64: orthonormalize_block<double>(rows, c, static_cast<double*>(Y), ldy, R_out, s, true); break;
+      case ISVD_FP32: orthonormalize_block<float>(rows, c, static_cast<float*>(Y), ldy, R_out, s, true); break;
+      case ISVD_BF16: orthonormalize_block<bf16>(rows, c, static_cast<bf16*>(Y), ldy, R_out, s, true); break;
       default: throw Error{ISVD_E_INVALID, "bad precision"};
     }
     return ISVD_OK;

@@ -18,6 +18,7 @@
 #include <utility>
 #include <vector>
 
+#include "householder.h"
 #include "operator.h"
 
 namespace isvd {
@@ -33,6 +34,8 @@ struct SvdState {
   // small FP64 matrices (padded lp x lp, ld lp)
   DevBuf G, R1, R2, Rc, Rtmp, Rcc, cs_work, sum_c, sum_r, Dc, flag, UR, ZR, sig, jac_work, rhs, left2, right2, gram_work, cn_work, sweeps;
   DevBuf Rc64, Dc64, Xf;   // row-register triangular solve: FP64 factor outputs, packed operands
+  bool householder = false;  // orthonormalise by Householder QR instead of Cholesky QR
+  DevBuf hh_q, hh_work, hh_cs;
   int iterations = 0, applies = 0, bf16_iterations = 0, checks = 0, fallback = 0, ritz_steps = 0;
   double residual = -1.0;
   bool have_ritz = false;
@@ -105,6 +108,19 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* cols
                     int npass = 2) {
   using C = typename ComputeOf<T>::type;
   const int l = st.l, lp = st.lp;
+  if (st.householder) {
+    // Algorithm 2's QR orthonormaliser: one Householder QR (backward stable, no second pass)
+    st.hh_q.ensure(static_cast<size_t>(rows) * st.ld * sizeof(T));
+    st.hh_work.ensure(householder_workspace_doubles(l) * sizeof(double));
+    launch_householder_qr<T>(rows, l, Y, st.ld, st.hh_q.as<T>(), st.ld, Rout, lp, st.hh_work.as<double>(), stream);
+    launch_convert<T, T>(rows, l, st.hh_q.as<T>(), st.ld, Y, st.ld, stream);
+    if (colsum) {
+      st.hh_cs.ensure(static_cast<size_t>(kColsumBlocks) * l * sizeof(double));
+      launch_colsum<T>(rows, l, Y, st.ld, st.hh_cs.as<double>(), colsum, stream);
+    }
+    (void)npass;
+    return;
+  }
   const bool use_inv = l <= trsm_rows_max_l(static_cast<int>(sizeof(C)));
   st.G.ensure(static_cast<size_t>(l) * l * sizeof(double));
   st.R1.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
@@ -533,6 +549,8 @@ isvd_status truncated_svd(isvd_operator* op, const isvd_svd_params* prm, void* U
   ISVD_CHECK(!(prm->tol > 0.0) || prm->max_iter >= 1, ISVD_E_INVALID, "tolerance mode needs max_iter >= 1");
   ISVD_CHECK(ldu >= st.k && ldv >= st.k, ISVD_E_INVALID, "ldu/ldv smaller than k");
   ISVD_CHECK(!prm->omega || prm->ld_omega >= st.l, ISVD_E_INVALID, "ld_omega smaller than k + p");
+  ISVD_CHECK(prm->orth_method == 0 || prm->orth_method == 1, ISVD_E_INVALID, "orth_method must be 0 or 1");
+  st.householder = prm->orth_method == 1;
   st.lp = pad16(st.l);
   st.ld = round_up(st.l, 8);
   isvd_status rc;
@@ -557,10 +575,12 @@ isvd_status truncated_svd(isvd_operator* op, const isvd_svd_params* prm, void* U
   return rc;
 }
 
-// Standalone CholeskyQR2 of one block.
+// Standalone CholeskyQR2 (or Householder QR) of one block.
 template <typename T>
-void orthonormalize_block(int64_t rows, int cols, T* Y, int64_t ld, double* Rout, hipStream_t stream) {
+void orthonormalize_block(int64_t rows, int cols, T* Y, int64_t ld, double* Rout, hipStream_t stream,
+                          bool householder) {
   SvdState st;
+  st.householder = householder;
   st.l = cols;
   st.lp = pad16(cols);
   st.ld = ld;
@@ -571,8 +591,8 @@ void orthonormalize_block(int64_t rows, int cols, T* Y, int64_t ld, double* Rout
   }
   ISVD_HIP(hipStreamSynchronize(stream));
 }
-template void orthonormalize_block<double>(int64_t, int, double*, int64_t, double*, hipStream_t);
-template void orthonormalize_block<float>(int64_t, int, float*, int64_t, double*, hipStream_t);
-template void orthonormalize_block<bf16>(int64_t, int, bf16*, int64_t, double*, hipStream_t);
+template void orthonormalize_block<double>(int64_t, int, double*, int64_t, double*, hipStream_t, bool);
+template void orthonormalize_block<float>(int64_t, int, float*, int64_t, double*, hipStream_t, bool);
+template void orthonormalize_block<bf16>(int64_t, int, bf16*, int64_t, double*, hipStream_t, bool);
 
 }  // namespace isvd

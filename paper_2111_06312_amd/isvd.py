@@ -47,7 +47,7 @@ class _SvdParams(ct.Structure):
     _fields_ = [("k", ct.c_int), ("p", ct.c_int), ("q", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
                 ("check_every", ct.c_int), ("seed", ct.c_uint64), ("omega", ct.c_void_p),
                 ("ld_omega", ct.c_int64), ("fp32_switch_tol", ct.c_double), ("bf16_max_iter", ct.c_int),
-                ("orth_passes", ct.c_int)]
+                ("orth_passes", ct.c_int), ("orth_method", ct.c_int)]
 
 
 class _SvdInfo(ct.Structure):
@@ -104,6 +104,7 @@ def load():
     lib.isvd_truncated_svd.argtypes = [vp, ct.POINTER(_SvdParams), vp, i64, vp, vp, i64, ct.POINTER(_SvdInfo), vp]
     lib.isvd_gaussian_block.argtypes = [i64, i64, ct.c_uint64, st, vp, i64, vp]
     lib.isvd_orthonormalize.argtypes = [i64, i64, st, vp, i64, vp, vp]
+    lib.isvd_orthonormalize_householder.argtypes = [i64, i64, st, vp, i64, vp, vp]
     lib.isvd_gram.argtypes = [i64, i64, i64, st, vp, i64, vp, i64, vp, i64, vp]
     lib.isvd_small_svd.argtypes = [i64, vp, vp, vp, vp, vp]
     lib.isvd_ws_features.argtypes = [vp, vp, vp]
@@ -225,7 +226,8 @@ class Operator:
         return out
 
     def truncated_svd(self, k, p, q=2, tol=0.0, max_iter=1000, check_every=0, seed=0, omega=None,
-                      fp32_switch_tol=0.0, bf16_max_iter=0, orth_passes=0, allow_not_converged=False):
+                      fp32_switch_tol=0.0, bf16_max_iter=0, orth_passes=0, allow_not_converged=False,
+                      orth_method=0):
         """(U, S, V, info) through isvd_truncated_svd."""
         r, c = self.shape
         out_dtype = torch.float32 if self.precision == BF16 else self.dtype
@@ -236,7 +238,7 @@ class Operator:
         prm = _SvdParams(k=k, p=p, q=q, tol=tol, max_iter=max_iter, check_every=check_every, seed=seed,
                          omega=_ptr(omega) if omega is not None else None,
                          ld_omega=_ld(omega) if omega is not None else 0, fp32_switch_tol=fp32_switch_tol,
-                         bf16_max_iter=bf16_max_iter, orth_passes=orth_passes)
+                         bf16_max_iter=bf16_max_iter, orth_passes=orth_passes, orth_method=orth_method)
         if omega is not None:
             assert omega.dtype == self.dtype and omega.shape == (c, k + p)
         info = _SvdInfo()
@@ -405,6 +407,15 @@ def orthonormalize(Y):
     l = Y.shape[1]
     R = torch.empty((l, l), dtype=torch.float64, device=Y.device)
     _check(_lib.isvd_orthonormalize(Y.shape[0], l, _PREC[Y.dtype], _ptr(Y), _ld(Y), _ptr(R), _stream()))
+    return Y, R
+
+
+def orthonormalize_householder(Y):
+    """In place Householder QR of Y; returns (Y, R) with R an FP64 tensor."""
+    load()
+    l = Y.shape[1]
+    R = torch.empty((l, l), dtype=torch.float64, device=Y.device)
+    _check(_lib.isvd_orthonormalize_householder(Y.shape[0], l, _PREC[Y.dtype], _ptr(Y), _ld(Y), _ptr(R), _stream()))
     return Y, R
 
 

@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c2", "c4", "c5"])
+    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16"])
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2000)
@@ -282,12 +282,38 @@ def learners_bench(args, lib, torch, np):
 def cpu_baseline(g, cfg, applies, orths):
     """Oracle timing on a bounded sample: one sparse product T @ P and one
     Householder QR of an n x l block, both FP64 at full size, scaled to the
-    products and orthonormalisations of one GPU run."""
+    products and orthonormalisations of one GPU run.  Feature form: one
+    product with M and one with M^T by the oracle's operator (materialised
+    blocks A_hat^j X) instead of the sparse product."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     from oracle.graph import adjacency, transition
     from oracle.isvd import orthonorm_qr
+
+    if cfg.form == "featprop":
+        from oracle.operators import FeatPropDesignMatrix
+        from synth import block_features
+        x = block_features(g.blocks, cfg.d, seed=1000 + cfg.index)
+        m = FeatPropDesignMatrix.from_graph(g, x, cfg.L)
+        rng = np.random.default_rng(0)
+        gm = rng.standard_normal((m.shape[1], cfg.l))
+        p = rng.standard_normal((g.n, cfg.l))
+        t0 = time.perf_counter()
+        _ = m.dot(gm)
+        _ = m.T.dot(p)
+        t_pair = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _ = orthonorm_qr(p)
+        t_qr = time.perf_counter() - t0
+        total = applies / 2 * t_pair + orths * t_qr
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        return {
+            "value": round(total, 3), "unit": "s", "cores": blas_threads, "kind": "oracle",
+            "sample": (f"one FP64 product pair M G, M^T P of the oracle's feature operator ({t_pair:.2f} s) and "
+                       f"one LAPACK QR of {g.n}x{cfg.l} ({t_qr:.2f} s, {blas_threads} BLAS threads) at full "
+                       f"size, scaled by {applies} products and {orths} QRs of the GPU run"),
+        }
 
     a = adjacency(g.n, g.indptr, g.indices, add_self_loops=cfg.self_loops)
     t = transition(a)
@@ -349,8 +375,13 @@ def main():
     g = make_graph(cfg)
     print(f"[bench] graph {cfg.name}: n={g.n} nnz={g.nnz} ({time.perf_counter() - t0:.1f} s)",
           file=sys.stderr, flush=True)
-    op = lib.Operator(g, form="ne", coeffs=cfg.coeffs, lam=cfg.lam, self_loops=cfg.self_loops,
-                      precision=precision)
+    if cfg.form == "featprop":
+        from synth import block_features
+        X = torch.as_tensor(block_features(g.blocks, cfg.d, seed=1000 + cfg.index)).cuda()
+        op = lib.Operator(g, form="featprop", X=X, L=cfg.L, precision=precision)
+    else:
+        op = lib.Operator(g, form="ne", coeffs=cfg.coeffs, lam=cfg.lam, self_loops=cfg.self_loops,
+                          precision=precision)
     kw = dict(tol=args.tol, max_iter=args.max_iter, check_every=args.check_every,
               fp32_switch_tol=args.fp32_switch_tol if precision == lib.BF16 else 0.0)
     ws = None
@@ -440,7 +471,8 @@ def main():
         "dtype": "bf16+f32" if precision == lib.BF16 else "f32",
         "data": "synthetic",
         "config": {"workload": cfg.name, "n": g.n, "nnz": int(g.nnz), "k": cfg.k, "p": cfg.p,
-                   "K": cfg.K, "lambda": cfg.lam, "tol": args.tol,
+                   **({"d": cfg.d, "L": cfg.L} if cfg.form == "featprop" else {"K": cfg.K, "lambda": cfg.lam}),
+                   "tol": args.tol,
                    "iterations": [i.iterations for i in infos], "applies": [i.applies for i in infos],
                    **({"bf16_iterations": [i.bf16_iterations for i in infos]} if precision == lib.BF16 else {}),
                    "residual": [i.residual for i in infos], "converged": converged,

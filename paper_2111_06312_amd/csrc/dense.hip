@@ -630,6 +630,138 @@ __global__ __launch_bounds__(256) void colpart_reduce_kernel(int nparts, int N, 
 constexpr int kColnormParts = 1024;
 constexpr int kTrsmParts = 1024;
 
+// FP32 C = alpha A B for K = 16 KC, KC in {4, 5, 8, 9} (no second A block, beta = 0):
+// the column block of B (K x 16 TN) is staged in LDS once per workgroup;
+// each wave takes 16-row tiles of A straight from memory into registers
+// (lane (li, lk) loads A[li][16 c + 4 lk .. +3] as one 16-byte word, c <
+// KC) and multiplies them with MFMA 16x16x4, step (c, e) taking
+// k = 16 c + e + 4 lk' over the four k-lanes (the same k order is used for
+// B's LDS rows, and the sum over k does not depend on it).  No barrier after
+// the B stage.
+constexpr int kGrWaves = 8;
+constexpr size_t kGrMaxLds = 96 * 1024;
+
+template <int TN, int KC>
+__global__ __launch_bounds__(64 * kGrWaves) void gemm_rows_kernel(int64_t M, int N, const float* A,
+                                                                  int64_t lda, const float* B, int64_t ldb,
+                                                                  float* Cm, int64_t ldc, float alpha,
+                                                                  int64_t row_tiles, int ldsb) {
+  extern __shared__ __align__(16) float gr_smem[];
+  const int K = 16 * KC;
+  const int col0 = static_cast<int>(blockIdx.y) * 16 * TN;
+  for (int f = threadIdx.x; f < K * 16 * TN; f += blockDim.x) {
+    const int r = f / (16 * TN), c = f - r * (16 * TN);
+    const int col = col0 + c;
+    gr_smem[r * ldsb + c] = col < N ? B[static_cast<int64_t>(r) * ldb + col] : 0.0f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kGrWaves;
+  // the next tile's A words are loaded while the current tile's MFMAs run
+  auto load_tile = [&](int64_t tile, v4f (&a)[KC]) {
+    const int64_t row = tile * 16 + li;
+    const bool ok = tile < row_tiles && row < M;
+    const float* ap = A + (ok ? row : 0) * lda + 4 * lk;
+#pragma unroll
+    for (int c = 0; c < KC; ++c) a[c] = ok ? *reinterpret_cast<const v4f*>(ap + 16 * c) : v4f{0.f, 0.f, 0.f, 0.f};
+  };
+  v4f a0[KC], a1[KC];
+  int64_t tile = static_cast<int64_t>(blockIdx.x) * kGrWaves + wave;
+  load_tile(tile, a0);
+  auto step = [&](int64_t t0, v4f (&cur)[KC], v4f (&nxt)[KC]) {
+    load_tile(t0 + stride, nxt);
+    v4f acc[TN];
+#pragma unroll
+    for (int t = 0; t < TN; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float* brow = gr_smem + (16 * c + 4 * lk + e) * ldsb + li;
+#pragma unroll
+        for (int t = 0; t < TN; ++t) acc[t] = mfma4(cur[c][e], brow[16 * t], acc[t]);
+        __builtin_amdgcn_sched_barrier(0);  // one k-step's B operands live at a time
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    float* crow[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) crow[r] = Cm + (t0 * 16 + drow<float>(lk, r)) * ldc + col0 + li;
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+      if (col0 + 16 * t + li < N) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (t0 * 16 + drow<float>(lk, r) < M) crow[r][16 * t] = alpha * acc[t][r];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  while (tile < row_tiles) {
+    step(tile, a0, a1);
+    tile += stride;
+    if (tile >= row_tiles) break;
+    step(tile, a1, a0);
+    tile += stride;
+  }
+}
+
+// Uses gemm_rows_kernel when the shape and alignment allow; returns false otherwise.
+bool gemm_rows_try(int64_t M, int N, int K, const float* A, int64_t lda, const float* B, int64_t ldb, float* Cm,
+                   int64_t ldc, double alpha, hipStream_t stream) {
+  const int kc = K / 16;
+  if (K % 16 != 0 || !(kc == 4 || kc == 5 || kc == 8 || kc == 9) || lda % 4 != 0 ||
+      reinterpret_cast<uintptr_t>(A) % 16 != 0)
+    return false;
+  const int tiles = static_cast<int>(ceil_div(N, 16));
+  int tn_max = static_cast<int>((kGrMaxLds / (sizeof(float) * K) - 4) / 16);
+  tn_max = std::min(tn_max, 11);
+  if (tn_max < 1) return false;
+  const int ncb = static_cast<int>(ceil_div(tiles, tn_max));
+  const int tn = static_cast<int>(ceil_div(tiles, ncb));
+  const int ldsb = 16 * tn + 4;
+  const size_t lds = static_cast<size_t>(K) * ldsb * sizeof(float);
+  const int64_t row_tiles = ceil_div(M, 16);
+  // one workgroup per compute unit and column block (B is staged once per workgroup)
+  static const int cus = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 256;
+    return n > 0 ? n : 256;
+  }();
+  const int64_t want = ceil_div(row_tiles, kGrWaves);
+  const unsigned gx = static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(want, std::max(1, cus / ncb))));
+  const dim3 grid(gx, static_cast<unsigned>(ncb)), block(64 * kGrWaves);
+  const float al = static_cast<float>(alpha);
+  auto go = [&](auto tn_c, auto kc_c) {
+    constexpr int TNv = decltype(tn_c)::value, KCv = decltype(kc_c)::value;
+    hipLaunchKernelGGL((gemm_rows_kernel<TNv, KCv>), grid, block, lds, stream, M, N, A, lda, B, ldb, Cm, ldc, al,
+                       row_tiles, ldsb);
+  };
+  auto with_kc = [&](auto tn_c) {
+    switch (K / 16) {
+      case 4: go(tn_c, std::integral_constant<int, 4>{}); return true;
+      case 5: go(tn_c, std::integral_constant<int, 5>{}); return true;
+      case 8: go(tn_c, std::integral_constant<int, 8>{}); return true;
+      case 9: go(tn_c, std::integral_constant<int, 9>{}); return true;
+      default: return false;
+    }
+  };
+  bool launched = false;
+  switch (tn) {
+#define ISVD_GR(X) \
+  case X: launched = with_kc(std::integral_constant<int, X>{}); break;
+    ISVD_GR(1) ISVD_GR(2) ISVD_GR(3) ISVD_GR(4) ISVD_GR(5) ISVD_GR(6) ISVD_GR(7) ISVD_GR(8) ISVD_GR(9)
+    ISVD_GR(10) ISVD_GR(11)
+#undef ISVD_GR
+    default: break;
+  }
+  if (!launched) return false;
+  ISVD_LAUNCH_CHECK();
+  return true;
+}
+
 template <typename T, typename C, int TN>
 void gemm_launch_tn(int64_t M, int N, int K1, const T* A1, int64_t lda1, int K2, const T* A2,
                     int64_t lda2, const C* B, int64_t ldb, T* Cm, int64_t ldc, double alpha,
@@ -1808,6 +1940,11 @@ void launch_gemm_tall(int64_t M, int N, int K1, const T* A1, int64_t lda1, int K
                       double* work, hipStream_t stream) {
   using C = typename ComputeOf<T>::type;
   if (M <= 0 || N <= 0) return;
+  if constexpr (std::is_same<T, float>::value) {
+    if (epi == GemmEpi::Store && K2 == 0 && beta == 0.0 &&
+        gemm_rows_try(M, N, K1, A1, lda1, B, ldb, Cm, ldc, alpha, stream))
+      return;
+  }
   const int tiles = static_cast<int>(ceil_div(N, 16));
   const int ncb = static_cast<int>(ceil_div(tiles, 8));
   const int tn = static_cast<int>(ceil_div(tiles, ncb));

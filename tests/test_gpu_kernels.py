@@ -225,3 +225,17 @@ def test_featprop_product(gpu_lib, precision, tol, L):
     out = to_np(gop.matmul(to_dev(q, dt), transpose=True))
     assert col_rel_err(out, oop.T.dot(q)) <= tol
     gop.close()
+
+
+@pytest.mark.parametrize("d,l,L", [(16, 7, 0), (48, 19, 1), (128, 80, 3), (256, 37, 0), (128, 176, 1)])
+def test_featprop_forward_gemm_shapes(gpu_lib, d, l, L):
+    # X [G_0 .. G_L] by the tall GEMM: K = d multiples of 16 (register-A path),
+    # ragged row count, column counts off the 16-column tiles
+    _print_case("featprop gemm", d, l, L)
+    g = sbm_graph(3001, 5, 0.004, 0.0004, seed=61)
+    x = block_features(g.blocks, d, seed=62)
+    gop, oop = featprop_pair(gpu_lib, g, x, L, 1)
+    gmat = rounded(gaussian_block(d * (L + 1), l, seed=63), torch.float32)
+    out = to_np(gop.matmul(to_dev(gmat, torch.float32)))
+    assert col_rel_err(out, oop.dot(gmat)) <= 2e-5
+    gop.close()

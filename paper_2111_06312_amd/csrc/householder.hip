@@ -20,6 +20,7 @@ namespace {
 constexpr int kHhThreads = 256;
 constexpr int kHhMaxCols = 1024;
 constexpr int kHhPer = kHhMaxCols / 64;   // columns per lane at most
+constexpr int kHhMaxParts = 1024;          // row slices of the dot-product pass
 
 // partial[b][k] = sum over this block's rows i >= j of V[i][j] W[i][k], k in [col0, l)
 template <typename T>
@@ -33,13 +34,24 @@ __global__ __launch_bounds__(kHhThreads) void hh_dots_kernel(int64_t rows, int l
   double acc[kHhPer];
 #pragma unroll
   for (int c = 0; c < kHhPer; ++c) acc[c] = 0.0;
-  for (int64_t i = r0 + wave; i < r1; i += kHhThreads / 64) {
-    const double vi = static_cast<double>(Elem<T>::load(V + i * ldv + j));
-    const T* w = W + i * ldw;
+  // four rows per step: their loads are independent and in flight together
+  constexpr int kRows = 4;
+  for (int64_t i0 = r0 + wave * kRows; i0 < r1; i0 += (kHhThreads / 64) * kRows) {
+    double vi[kRows];
+    const T* w[kRows];
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+      const int64_t i = i0 + q < r1 ? i0 + q : r0;
+      vi[q] = i0 + q < r1 ? static_cast<double>(Elem<T>::load(V + i * ldv + j)) : 0.0;
+      w[q] = W + i * ldw;
+    }
 #pragma unroll
     for (int c = 0; c < kHhPer; ++c) {
       const int k = col0 + lane + 64 * c;
-      if (k < l) acc[c] += vi * static_cast<double>(Elem<T>::load(w + k));
+      if (k < l) {
+#pragma unroll
+        for (int q = 0; q < kRows; ++q) acc[c] += vi[q] * static_cast<double>(Elem<T>::load(w[q] + k));
+      }
     }
   }
 #pragma unroll
@@ -56,6 +68,21 @@ __global__ __launch_bounds__(kHhThreads) void hh_dots_kernel(int64_t rows, int l
   }
 }
 
+// sum over p < nparts of partial[p][k], four sums with several loads in flight
+__device__ inline double sum_parts(const double* partial, int nparts, int l, int k) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int p = 0;
+#pragma unroll 2
+  for (; p + 3 < nparts; p += 4) {
+    s0 += partial[static_cast<int64_t>(p) * l + k];
+    s1 += partial[static_cast<int64_t>(p + 1) * l + k];
+    s2 += partial[static_cast<int64_t>(p + 2) * l + k];
+    s3 += partial[static_cast<int64_t>(p + 3) * l + k];
+  }
+  for (; p < nparts; ++p) s0 += partial[static_cast<int64_t>(p) * l + k];
+  return (s0 + s1) + (s2 + s3);
+}
+
 // Reflector of column j from the reduced dot products (one block).
 template <typename T>
 __global__ __launch_bounds__(kHhThreads) void hh_reflect_kernel(int l, int j, int nparts, const double* partial,
@@ -63,11 +90,7 @@ __global__ __launch_bounds__(kHhThreads) void hh_reflect_kernel(int l, int j, in
                                                                 double* beta) {
   __shared__ double d[kHhMaxCols];
   __shared__ double sh[2];
-  for (int k = j + static_cast<int>(threadIdx.x); k < l; k += kHhThreads) {
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += partial[static_cast<int64_t>(p) * l + k];
-    d[k] = s;
-  }
+  for (int k = j + static_cast<int>(threadIdx.x); k < l; k += kHhThreads) d[k] = sum_parts(partial, nparts, l, k);
   __syncthreads();
   if (threadIdx.x == 0) {
     const double ajj = static_cast<double>(Elem<T>::load(Y + static_cast<int64_t>(j) * ld + j));
@@ -90,11 +113,7 @@ __global__ __launch_bounds__(kHhThreads) void hh_reflect_kernel(int l, int j, in
 // g_k = beta_j z_k for the backward formation of Q (one block).
 __global__ __launch_bounds__(kHhThreads) void hh_scale_kernel(int l, int j, int nparts, const double* partial,
                                                               const double* beta, double* g) {
-  for (int k = j + static_cast<int>(threadIdx.x); k < l; k += kHhThreads) {
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += partial[static_cast<int64_t>(p) * l + k];
-    g[k] = beta[j] * s;
-  }
+  for (int k = j + static_cast<int>(threadIdx.x); k < l; k += kHhThreads) g[k] = beta[j] * sum_parts(partial, nparts, l, k);
 }
 
 // W[i][k] -= V[i][j] g_k for rows i >= j, columns k in [col0, l): one wave per row.
@@ -140,19 +159,21 @@ __global__ void hh_extract_r_kernel(int l, int lp, const T* Y, int64_t ld, const
 }
 
 int parts_for(int64_t rows, int j) {
-  return static_cast<int>(std::min<int64_t>(256, std::max<int64_t>(1, ceil_div(rows - j, 256))));
+  return static_cast<int>(std::min<int64_t>(kHhMaxParts, std::max<int64_t>(1, ceil_div(rows - j, 64))));
 }
 
 }  // namespace
 
-size_t householder_workspace_doubles(int l) { return static_cast<size_t>(256) * l + 3 * static_cast<size_t>(l); }
+size_t householder_workspace_doubles(int l) {
+  return static_cast<size_t>(kHhMaxParts) * l + 3 * static_cast<size_t>(l);
+}
 
 template <typename T>
 void launch_householder_qr(int64_t rows, int l, T* Y, int64_t ld, T* Q, int64_t ldq, double* R, int lp,
                            double* work, hipStream_t stream) {
   ISVD_CHECK(l >= 1 && l <= kHhMaxCols && rows >= l, ISVD_E_INVALID, "householder: need 1 <= l <= min(rows, 1024)");
   double* partial = work;
-  double* g = work + static_cast<size_t>(256) * l;
+  double* g = work + static_cast<size_t>(kHhMaxParts) * l;
   double* alpha = g + l;
   double* beta = alpha + l;
   const unsigned upd_blocks = static_cast<unsigned>(std::min<int64_t>(ceil_div(rows, 4), 16384));

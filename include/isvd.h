@@ -267,8 +267,9 @@ isvd_status isvd_small_svd(int64_t n, const double* A, double* Uo, double* s, do
  * A DAG has one precision (ISVD_FP64 or ISVD_FP32): its dense leaves and
  * every block it multiplies are of that type.  Node ids are returned in
  * *id (>= 0).  Leaves borrow their device arrays (valid and unchanged while
- * the DAG lives) except where copied is said.  The DAG must outlive every
- * operator made from it.  Building nodes launches no GPU work except for
+ * the DAG or any operator made from it lives) except where copied is said.
+ * Operators share the DAG's nodes: the DAG handle may be destroyed before
+ * them.  Building nodes launches no GPU work except for
  * isvd_dag_diag and isvd_dag_gather_rows (copies, synchronised).
  *
  * Evaluation (isvd_matmul_block on a DAG operator): products are flattened
@@ -286,7 +287,8 @@ isvd_status isvd_small_svd(int64_t n, const double* A, double* Uo, double* s, do
 typedef struct isvd_dag isvd_dag;
 
 isvd_status isvd_dag_create(isvd_precision precision, isvd_dag** out);
-/* Releases the DAG (NULL ignored); its operators must be destroyed first. */
+/* Releases the DAG handle (NULL ignored); operators made from it keep its
+ * nodes until they are destroyed. */
 void isvd_dag_destroy(isvd_dag* dag);
 
 /* Sparse leaf (rows x cols CSR, device, borrowed; values NULL = all ones).
@@ -318,8 +320,8 @@ isvd_status isvd_dag_gather_rows(isvd_dag* dag, int64_t node, const int64_t* row
 isvd_status isvd_dag_concat_cols(isvd_dag* dag, int count, const int64_t* ids, int64_t* id);
 /* (rows, cols) of a node (host outputs). */
 isvd_status isvd_dag_shape(const isvd_dag* dag, int64_t node, int64_t* rows, int64_t* cols);
-/* An operator for node `root` (form ISVD_FORM_DAG).  Destroy it with
- * isvd_destroy_operator before the DAG. */
+/* An operator for node `root` (form ISVD_FORM_DAG); release it with
+ * isvd_destroy_operator. */
 isvd_status isvd_dag_operator(isvd_dag* dag, int64_t root, int lazy_cache, isvd_operator** out);
 
 /* ---------------------------------------------------------------------------

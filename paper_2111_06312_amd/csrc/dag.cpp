@@ -39,7 +39,7 @@ using Chain = std::vector<Atom>;
 }  // namespace
 
 struct DagEval {
-  const isvd_dag* dag = nullptr;
+  std::shared_ptr<const std::vector<std::unique_ptr<DagNode>>> nodes;  // shared with the DAG
   int64_t root = 0;
   bool cache_on = true;
   // block pool (grown on demand, kept between products)
@@ -57,7 +57,7 @@ struct View {
   int owner = -1;  // pool slot the caller must release, -1: borrowed (input or cache)
 };
 
-const DagNode& node_of(const DagEval& ev, int64_t id) { return *ev.dag->nodes[static_cast<size_t>(id)]; }
+const DagNode& node_of(const DagEval& ev, int64_t id) { return *(*ev.nodes)[static_cast<size_t>(id)]; }
 
 // Rows of the result of applying an atom (a factor of the chain).
 int64_t out_rows(const DagEval& ev, const Atom& a) {
@@ -452,7 +452,7 @@ class Evaluator {
 
 std::shared_ptr<DagEval> make_dag_eval(const isvd_dag* dag, int64_t root, bool lazy_cache) {
   auto ev = std::make_shared<DagEval>();
-  ev->dag = dag;
+  ev->nodes = dag->store;
   ev->root = root;
   ev->cache_on = lazy_cache;
   return ev;

@@ -36,13 +36,18 @@ void launch_diag_scale(int64_t rows, int cols, const double* d, const T* X, int6
 // Evaluator state of one operator (a root node of a DAG).
 struct DagEval;
 std::shared_ptr<DagEval> make_dag_eval(const isvd_dag* dag, int64_t root, bool lazy_cache);
+using DagStore = std::vector<std::unique_ptr<DagNode>>;
 template <typename T>
 void dag_apply(DagEval& ev, bool transpose, const T* Y, int64_t ldy, int ncols, T* out, int64_t ldo,
                hipStream_t stream);
 
 }  // namespace isvd
 
+// The node store is shared with the operators made from the DAG, so that an
+// operator stays valid if the DAG handle is destroyed first.
 struct isvd_dag {
   isvd_precision prec = ISVD_FP32;
-  std::vector<std::unique_ptr<isvd::DagNode>> nodes;
+  std::shared_ptr<std::vector<std::unique_ptr<isvd::DagNode>>> store =
+      std::make_shared<std::vector<std::unique_ptr<isvd::DagNode>>>();
+  std::vector<std::unique_ptr<isvd::DagNode>>& nodes = *store;
 };

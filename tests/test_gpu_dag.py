@@ -190,3 +190,18 @@ def test_svd_of_a_dag_operator_matches_the_oracle(gpu_lib):
     assert principal_angles(to_np(U)[:, :kk], uo[:, :kk]).max() <= 1e-8
     op.close()
     dag.close()
+
+
+def test_operator_outlives_its_dag_handle(gpu_lib):
+    _case("dag lifetime")
+    g = chung_lu_graph(2000, 2.5, 8.0, seed=44)
+    coeffs = np.array([0.5, 0.5])
+    dag, op = _fig1(gpu_lib, g, coeffs, 0.1, 0)
+    y = to_dev(gaussian_block(g.n, 5, seed=6), torch.float64)
+    before = to_np(op.matmul(y))
+    keep = dag._keep                   # the leaves' device arrays stay alive (caller's side)
+    dag.close()                        # the operator keeps the nodes
+    after = to_np(op.matmul(y))
+    assert np.array_equal(before, after)
+    op.close()
+    del keep

@@ -51,3 +51,60 @@ def test_graph_validation_before_any_device_work(lib):
     h = ct.c_void_p()
     assert lib.isvd_create_operator(ct.byref(g), ct.byref(d), 1, None, ct.byref(h)) == isvd.ISVD_E_INVALID
     assert b"n > 0" in lib.isvd_last_error()
+
+
+def test_symbolic_dag_shapes_and_validation_without_a_gpu(lib):
+    # building dense leaves, sums, products, transposes and concatenations is
+    # host bookkeeping (a dense leaf's pointer is only kept, never read here)
+    i64 = ct.c_int64
+    dag = ct.c_void_p()
+    assert lib.isvd_dag_create(isvd.BF16, ct.byref(dag)) == isvd.ISVD_E_INVALID   # FP32 / FP64 only
+    assert lib.isvd_dag_create(isvd.FP32, ct.byref(dag)) == isvd.ISVD_OK
+    buf = (ct.c_float * 64)()
+    ptr = ct.cast(buf, ct.c_void_p)
+
+    def dense(r, c):
+        out = i64()
+        assert lib.isvd_dag_dense(dag, r, c, ptr, c, ct.byref(out)) == isvd.ISVD_OK
+        return out.value
+
+    def shape(node):
+        r, c = i64(), i64()
+        assert lib.isvd_dag_shape(dag, node, ct.byref(r), ct.byref(c)) == isvd.ISVD_OK
+        return r.value, c.value
+
+    def ids(*xs):
+        return (i64 * len(xs))(*xs)
+
+    a, b = dense(100, 7), dense(7, 5)          # shapes only: the leaf rows are never multiplied here
+    out = i64()
+    assert lib.isvd_dag_product(dag, 2, ids(a, b), ct.byref(out)) == isvd.ISVD_OK
+    ab = out.value
+    assert shape(ab) == (100, 5)
+    assert lib.isvd_dag_transpose(dag, ab, ct.byref(out)) == isvd.ISVD_OK
+    assert shape(out.value) == (5, 100)
+    assert lib.isvd_dag_concat_cols(dag, 2, ids(a, ab), ct.byref(out)) == isvd.ISVD_OK
+    assert shape(out.value) == (100, 12)
+    w = (ct.c_double * 2)(1.0, -2.0)
+    assert lib.isvd_dag_sum(dag, 2, ids(ab, ab), w, ct.byref(out)) == isvd.ISVD_OK
+    assert shape(out.value) == (100, 5)
+    # errors: inner dimensions, term shapes, concatenation rows, node ids, leaf widths
+    assert lib.isvd_dag_product(dag, 2, ids(a, a), ct.byref(out)) == isvd.ISVD_E_INVALID
+    assert lib.isvd_dag_sum(dag, 2, ids(a, ab), None, ct.byref(out)) == isvd.ISVD_E_INVALID
+    assert lib.isvd_dag_concat_cols(dag, 2, ids(a, b), ct.byref(out)) == isvd.ISVD_E_INVALID
+    assert lib.isvd_dag_transpose(dag, 999, ct.byref(out)) == isvd.ISVD_E_INVALID
+    assert lib.isvd_dag_dense(dag, 10, 4096, ptr, 4096, ct.byref(out)) == isvd.ISVD_E_INVALID
+    assert lib.isvd_dag_dense(dag, 10, 4, ptr, 3, ct.byref(out)) == isvd.ISVD_E_INVALID
+    lib.isvd_dag_destroy(dag)
+
+
+def test_learner_argument_errors_without_a_gpu(lib):
+    # checks that fail before any device work
+    p = ct.c_void_p(16)
+    assert lib.isvd_ne_embeddings(10, 10, 4, isvd.BF16, p, 4, p, p, 4, p, 4, p, 4, None) == isvd.ISVD_E_INVALID
+    assert lib.isvd_ne_scores(0, isvd.FP32, p, 4, 10, p, p, 4, 10, 1, p, p, p, None) == isvd.ISVD_E_INVALID
+    assert lib.isvd_nc_fit(10, 10, 4, 2045, isvd.FP32, p, 4, p, p, 4, p, 2045, None, -1, 0.0, p, 2045,
+                           None) == isvd.ISVD_E_INVALID                       # k + ny > 2048
+    assert lib.isvd_nc_fit(10, 10, 4, 2, isvd.FP32, p, 4, p, p, 4, p, 2, None, 5, 0.0, p, 2,
+                           None) == isvd.ISVD_E_INVALID                       # nsub > 0 without rows
+    assert lib.isvd_orthonormalize_householder(3, 5, isvd.FP32, p, 5, None, None) == isvd.ISVD_E_INVALID

@@ -381,8 +381,10 @@ void ws_train_step(isvd_warmstart* ws, int64_t n, const float* F, const float* V
   size_t wneed = gw;
   const size_t g2 = gram_workspace_doubles(n, kHid, kHid > k ? kHid : k);
   const size_t g3 = gram_workspace_doubles(n, kIn, kHid);
+  const size_t g4 = gram_workspace_doubles(n, kHid, k);   // each Gram shape below sizes its own slices
   wneed = wneed > g2 ? wneed : g2;
   wneed = wneed > g3 ? wneed : g3;
+  wneed = wneed > g4 ? wneed : g4;
   ws->work.ensure(wneed * sizeof(double));
   double* work = ws->work.as<double>();
   launch_gram<float>(n, k, k, Z, k, Z, k, true, G, k, work, s);

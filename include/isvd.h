@@ -15,6 +15,9 @@
  *                      builds the same matrix symbolically).
  *   ISVD_FORM_FEATPROP M = [X, Ahat X, Ahat^2 X, ..., Ahat^L X],  n x d(L+1)
  *                      with Ahat = (D+I)^-1/2 (A+I) (D+I)^-1/2 (Section 2, Eq. 7).
+ * Any other M can be built as a symbolic DAG (isvd_dag_*, Section 4) and
+ * used through the same operator entry points; on top of the SVD sit the
+ * closed-form learners of Section 3 (isvd_ne_*, isvd_nc_fit).
  *
  * Conventions (all entry points):
  *  - Every array argument is DEVICE memory unless its comment says "host".

@@ -126,6 +126,7 @@ def test_every_node_type_against_the_oracle(gpu_lib, precision):
     D = dag.diag(d)
     oA, oC, oB, oD = SparsePF(a), SparsePF(c), DensePF(b), DiagPF(d)
     rows = rng.choice(700, 250, replace=False)
+    cols = np.random.default_rng(70).choice(500, 120, replace=False)
     cases = [
         (A, oA),
         (B, oB),
@@ -136,6 +137,8 @@ def test_every_node_type_against_the_oracle(gpu_lib, precision):
         ((C @ A).gather_rows(rows).T, GatherRowsPF(oC @ oA, rows).T),
         (dag.concat_cols([A, C, D @ A]), ConcatColsPF([oA, oC, oD @ oA])),
         (dag.concat_cols([A, C]).T, ConcatColsPF([oA, oC]).T),
+        # a column gather M[:, cols] is the transpose of a row gather of M^T
+        ((C @ A).T.gather_rows(cols).T, GatherRowsPF((oC @ oA).T, cols).T),
         (2.0 * (C @ C + D) @ C - C, 2.0 * (oC @ oC + oD) @ oC - oC),
     ]
     for i, (node, ref) in enumerate(cases):

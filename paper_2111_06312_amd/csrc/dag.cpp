@@ -327,7 +327,13 @@ class Evaluator {
  private:
   // The terms of the sum or column concatenation at chain[pos], each
   // continued by the rest of the chain, accumulated into out with `scale`.
+  // A term that is itself a sum or column concatenation (and not already in
+  // the cache) is expanded in place, so nested sums add straight into `out`.
   void sum_terms(const Chain& chain, size_t pos, double scale, const View<T>& out) {
+    bool first = true;
+    sum_terms(chain, pos, scale, out, first);
+  }
+  void sum_terms(const Chain& chain, size_t pos, double scale, const View<T>& out, bool& first) {
     const Atom& a = chain[pos];
     const DagNode& n = node_of(ev_, a.node);
     for (size_t k = 0; k < n.kids.size(); ++k) {
@@ -336,7 +342,15 @@ class Evaluator {
       flatten(ev_, n.kids[k], a.t, c, coef);
       if (n.kind == DagKind::Concat) c.push_back({Atom::Slice, a.node, false, static_cast<int>(k)});
       c.insert(c.end(), chain.begin() + static_cast<std::ptrdiff_t>(pos) + 1, chain.end());
-      accumulate(c, coef, out, k == 0);
+      if (c[0].kind == Atom::Node && !(ev_.cache_on && cache_.count(c))) {
+        const DagNode& h = node_of(ev_, c[0].node);
+        if (h.kind == DagKind::Sum || (h.kind == DagKind::Concat && !c[0].t)) {
+          sum_terms(c, 0, coef, out, first);
+          continue;
+        }
+      }
+      accumulate(c, coef, out, first);
+      first = false;
     }
   }
 

@@ -239,9 +239,6 @@ isvd_status isvd_gaussian_block(int64_t rows, int64_t cols, uint64_t seed, isvd_
 isvd_status isvd_orthonormalize(int64_t rows, int64_t cols, isvd_precision precision, void* Y,
                                 int64_t ldy, double* R_out, void* stream);
 
-/* C = A^T B, A rows x m, B rows x p (same precision, leading dimensions lda,
- * ldb, m + p <= 2048), C m x p FP64 row-major (ldc), products formed exactly
- * and summed in FP64 in a fixed order.  Synchronises the stream. */
 /* Householder QR of Y (rows x cols, in place: Y <- Q; R_out optional, as for
  * isvd_orthonormalize but R's diagonal may be negative), Algorithm 2's QR
  * orthonormaliser: unblocked, two passes over the trailing block per column
@@ -250,6 +247,10 @@ isvd_status isvd_orthonormalize(int64_t rows, int64_t cols, isvd_precision preci
 isvd_status isvd_orthonormalize_householder(int64_t rows, int64_t cols, isvd_precision precision, void* Y,
                                             int64_t ldy, double* R_out, void* stream);
 
+/* C = A^T B, A rows x m, B rows x p (same precision, leading dimensions lda,
+ * ldb, m + p <= 2048), C m x p FP64 row-major (ldc), products formed exactly
+ * and summed in FP64 in a fixed order.  Synchronises the stream.
+ * The Gram matrices of Algorithm 2's Cholesky orthonormaliser. */
 isvd_status isvd_gram(int64_t rows, int64_t m, int64_t p, isvd_precision precision, const void* A,
                       int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc, void* stream);
 

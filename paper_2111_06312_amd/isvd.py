@@ -152,22 +152,40 @@ def _ld(t):
 class Operator:
     """Implicit design matrix on the GPU (isvd_create_operator).
 
-    graph: synth.Graph (host arrays are copied to the device and kept alive).
+    graph: an object with n, nnz, indptr (n+1 offsets) and indices (column
+           ids) of the CSR of A, e.g. synth.Graph (host arrays are copied to
+           the device and kept alive).
     form : "ne" (coeffs, lam, self_loops) or "featprop" (X torch tensor, L).
+    values: edge weights of A in CSR order (None: every entry is 1).
+    symmetric: A == A^T; otherwise t_indptr / t_indices (/ t_values, given
+           exactly when values is) hold the CSR of A^T.
     """
 
     def __init__(self, graph, form="ne", coeffs=None, lam=0.0, self_loops=False, X=None, L=0,
-                 precision=FP32, device="cuda"):
+                 precision=FP32, device="cuda", values=None, symmetric=True, t_indptr=None, t_indices=None,
+                 t_values=None):
         lib = load()
         self.precision = precision
         self.dtype = _DTYPE[precision]
         self.n = graph.n
-        self._indptr = torch.as_tensor(np.asarray(graph.indptr, dtype=np.int64), device=device)
-        self._indices = torch.as_tensor(np.asarray(graph.indices, dtype=np.int32), device=device)
-        if self._indices.numel() == 0:
-            self._indices = torch.zeros(1, dtype=torch.int32, device=device)
+
+        def dev(a, dt, nonempty=False):
+            if a is None:
+                return None
+            t = torch.as_tensor(np.ascontiguousarray(np.asarray(a, dtype=dt)), device=device)
+            if nonempty and t.numel() == 0:
+                t = torch.zeros(1, dtype=t.dtype, device=device)
+            return t
+
+        self._indptr = dev(graph.indptr, np.int64)
+        self._indices = dev(graph.indices, np.int32, nonempty=True)
+        self._values = dev(values, np.float32, nonempty=True)
+        self._t_indptr = dev(t_indptr, np.int64)
+        self._t_indices = dev(t_indices, np.int32, nonempty=True)
+        self._t_values = dev(t_values, np.float32, nonempty=True)
         g = _Graph(n=graph.n, nnz=graph.nnz, indptr=self._indptr.data_ptr(), indices=self._indices.data_ptr(),
-                   values=None, symmetric=1, t_indptr=None, t_indices=None, t_values=None,
+                   values=_ptr(self._values), symmetric=1 if symmetric else 0, t_indptr=_ptr(self._t_indptr),
+                   t_indices=_ptr(self._t_indices), t_values=_ptr(self._t_values),
                    add_self_loops=1 if self_loops else 0)
         if form == "ne":
             c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
@@ -282,6 +300,14 @@ class Dag:
         _check(fn(self.handle, *args, ct.byref(out)))
         return DagNode(self, out.value)
 
+    def _ids(self, nodes):
+        """Node ids as a C array; every node must belong to this DAG (an id
+        is an index into one DAG's node store and means nothing in another)."""
+        for nd in nodes:
+            if not isinstance(nd, DagNode) or nd.dag is not self:
+                raise ValueError("node belongs to another Dag")
+        return (ct.c_int64 * len(nodes))(*[nd.id for nd in nodes])
+
     def sparse(self, indptr, indices, shape, values=None, symmetric=True, t_indptr=None, t_indices=None,
                t_values=None):
         """CSR leaf (host or device arrays; copied to the device and kept)."""
@@ -308,19 +334,20 @@ class Dag:
         return self._node(_lib.isvd_dag_diag, t.shape[0], _ptr(t))
 
     def sum(self, nodes, weights=None):
-        ids = (ct.c_int64 * len(nodes))(*[n.id for n in nodes])
+        ids = self._ids(nodes)
         w = None if weights is None else (ct.c_double * len(nodes))(*[float(x) for x in weights])
         return self._node(_lib.isvd_dag_sum, len(nodes), ids, w)
 
     def product(self, nodes):
-        ids = (ct.c_int64 * len(nodes))(*[n.id for n in nodes])
+        ids = self._ids(nodes)
         return self._node(_lib.isvd_dag_product, len(nodes), ids)
 
     def concat_cols(self, nodes):
-        ids = (ct.c_int64 * len(nodes))(*[n.id for n in nodes])
+        ids = self._ids(nodes)
         return self._node(_lib.isvd_dag_concat_cols, len(nodes), ids)
 
     def operator(self, node, lazy_cache=True):
+        self._ids([node])
         h = ct.c_void_p()
         _check(_lib.isvd_dag_operator(self.handle, node.id, 1 if lazy_cache else 0, ct.byref(h)))
         op = Operator.__new__(Operator)

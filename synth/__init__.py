@@ -13,6 +13,9 @@ from .graphs import (  # noqa: F401
     cycle_graph,
     complete_graph,
     edges_to_csr,
+    DirectedGraph,
+    directed_graph,
+    csr_transpose,
 )
 from .inputs import block_features, gaussian_block  # noqa: F401
 from .configs import CONFIGS, WorkloadConfig, make_workload  # noqa: F401

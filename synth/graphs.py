@@ -209,3 +209,81 @@ def random_pattern(n_rows: int, n_cols: int, density: float, seed: int, hub_rows
         if ln:
             indices[indptr[r]:indptr[r + 1]] = np.sort(rng.choice(n_cols, size=ln, replace=False))
     return indptr, indices
+
+
+@dataclass
+class DirectedGraph:
+    """Directed, optionally weighted graph: the CSR of A and the CSR of A^T.
+
+    indptr / t_indptr : int64 arrays of n+1 row offsets of A / of A^T
+    indices / t_indices : int32 column indices, sorted inside each row
+    values / t_values : float32 edge weights in the same order, or None
+                        (every stored entry is 1)
+    """
+
+    n: int
+    indptr: np.ndarray
+    indices: np.ndarray
+    values: np.ndarray | None
+    t_indptr: np.ndarray
+    t_indices: np.ndarray
+    t_values: np.ndarray | None
+    blocks: np.ndarray | None = None
+
+    @property
+    def nnz(self) -> int:
+        return int(self.indptr[-1])
+
+    def row_lengths(self) -> np.ndarray:
+        return np.diff(self.indptr)
+
+
+def csr_transpose(n_rows: int, n_cols: int, indptr, indices, values=None):
+    """CSR arrays of the transpose (a format conversion: entries are only
+    moved, never combined).  Returns (indptr int64, indices int32, values
+    or None), column indices sorted inside each row."""
+    indptr = np.asarray(indptr, dtype=np.int64)
+    indices = np.asarray(indices, dtype=np.int64)
+    rows = np.repeat(np.arange(n_rows, dtype=np.int64), np.diff(indptr))
+    order = np.lexsort((rows, indices))          # by column, then by row
+    t_indptr = np.zeros(n_cols + 1, dtype=np.int64)
+    np.cumsum(np.bincount(indices, minlength=n_cols), out=t_indptr[1:])
+    t_values = None if values is None else np.asarray(values)[order]
+    return t_indptr, rows[order].astype(np.int32), t_values
+
+
+def directed_graph(n: int, mean_degree: float, seed: int, weighted: bool = True, hub_rows: int = 0,
+                   hub_len: int = 0, hub_cols: int = 0, hub_col_len: int = 0, empty_rows: int = 0,
+                   w_range=(0.25, 2.0)) -> DirectedGraph:
+    """Random directed graph for tests of a general (non-symmetric) A.
+
+    Each node draws Binomial out-edges to uniform targets (mean
+    `mean_degree`); `hub_rows` nodes get `hub_len` out-edges and
+    `hub_cols` nodes receive `hub_col_len` extra in-edges (long rows of A
+    and of A^T); `empty_rows` nodes have no out-edges at all (zero
+    out-degree).  Self-pairs and repeated pairs are dropped.  With
+    `weighted`, each edge carries a weight ~ U[w_range], rounded to
+    float32."""
+    rng = np.random.default_rng(seed)
+    lens = rng.binomial(n - 1, min(mean_degree / max(n - 1, 1), 1.0), size=n).astype(np.int64)
+    hubs = rng.choice(n, size=min(hub_rows, n), replace=False) if hub_rows else np.empty(0, np.int64)
+    lens[hubs] = min(hub_len, n - 1)
+    src = np.repeat(np.arange(n, dtype=np.int64), lens)
+    dst = rng.integers(0, n, src.shape[0])
+    if hub_cols:
+        targets = rng.choice(n, size=min(hub_cols, n), replace=False)
+        src = np.concatenate([src, rng.integers(0, n, targets.shape[0] * hub_col_len)])
+        dst = np.concatenate([dst, np.repeat(targets, hub_col_len)])
+    empty = rng.choice(np.setdiff1d(np.arange(n), hubs), size=min(empty_rows, n - hubs.shape[0]),
+                       replace=False) if empty_rows else np.empty(0, np.int64)
+    keep = (src != dst) & ~np.isin(src, empty)
+    code = np.unique(src[keep] * n + dst[keep])
+    rows, cols = code // n, code % n
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=indptr[1:])
+    values = None
+    if weighted:
+        values = rng.uniform(w_range[0], w_range[1], rows.shape[0]).astype(np.float32)
+    t_indptr, t_indices, t_values = csr_transpose(n, n, indptr, cols, values)
+    return DirectedGraph(n=n, indptr=indptr, indices=cols.astype(np.int32), values=values,
+                         t_indptr=t_indptr, t_indices=t_indices, t_values=t_values)

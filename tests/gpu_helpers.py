@@ -50,3 +50,30 @@ def gapped_k(s_all, k, rel_gap=1e-3):
         if (s_all[kk - 1] - s_all[kk]) / s_all[kk - 1] >= rel_gap:
             return kk
     return 0
+
+
+def ne_pair_general(lib, dg, coeffs, lam, loops, precision, weighted=True):
+    """GPU and oracle NE operators of a directed (optionally weighted)
+    synth.DirectedGraph: the GPU side gets the CSR of A and of A^T, the
+    oracle builds its own transpose from A."""
+    vals = dg.values if weighted else None
+    tvals = dg.t_values if weighted else None
+    gop = lib.Operator(dg, form="ne", coeffs=coeffs, lam=lam, self_loops=loops, precision=precision,
+                       values=vals, symmetric=False, t_indptr=dg.t_indptr, t_indices=dg.t_indices,
+                       t_values=tvals)
+    oop = NEDesignMatrix.from_graph(dg, coeffs, lam, add_self_loops=loops,
+                                    values=None if vals is None else vals.astype(np.float64))
+    return gop, oop
+
+
+def sampled_triplets(k):
+    """Ten triplet indices spread over 0..k-1, the first two and the last
+    two included."""
+    return np.unique(np.concatenate([[0, 1], np.linspace(2, k - 3, 6).round().astype(int), [k - 2, k - 1]]))
+
+
+# The device evaluates rho from the blocks it stores (FP32 products of the
+# FP32 triplets; the FP64 oracle evaluates the same triplets exactly).  The
+# two differ by the FP32 rounding of those products, about 1e-6 relative
+# here, so a returned rho at the tolerance can read up to 1% above it.
+RHO_SLACK = 1.01

@@ -108,3 +108,20 @@ def test_learner_argument_errors_without_a_gpu(lib):
     assert lib.isvd_nc_fit(10, 10, 4, 2, isvd.FP32, p, 4, p, p, 4, p, 2, None, 5, 0.0, p, 2,
                            None) == isvd.ISVD_E_INVALID                       # nsub > 0 without rows
     assert lib.isvd_orthonormalize_householder(3, 5, isvd.FP32, p, 5, None, None) == isvd.ISVD_E_INVALID
+
+
+def test_binding_rejects_nodes_of_another_dag(lib):
+    # a node id indexes one DAG's node store; handing it to another DAG must
+    # fail in the binding instead of silently naming a different node
+    buf = (ct.c_float * 64)()
+    ptr = ct.cast(buf, ct.c_void_p)
+    d1, d2 = isvd.Dag(isvd.FP32), isvd.Dag(isvd.FP32)
+    a = d1._node(lib.isvd_dag_dense, 8, 8, ptr, 8)       # host pointer: shape bookkeeping only
+    b = d2._node(lib.isvd_dag_dense, 8, 8, ptr, 8)
+    assert d1.sum([a, a]).shape == (8, 8)
+    for bad in (lambda: d1.sum([a, b]), lambda: d1.product([a, b]), lambda: d1.concat_cols([b]),
+                lambda: a + b, lambda: a @ b, lambda: d1.operator(b)):
+        with pytest.raises(ValueError):
+            bad()
+    d1.close()
+    d2.close()

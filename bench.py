@@ -3,16 +3,23 @@
 One step = one isvd_truncated_svd call in tolerance mode (every product,
 orthonormalisation, Rayleigh-Ritz step and residual check of the method)
 on a resident synthetic graph; the start block is drawn on the device
-inside the call.  Default workload: Chung-Lu power-law graph, n = 200,000,
-exponent 2.5, mean degree 20, M = (1/10) sum_{j=1..10} T^j - 0.1 (11^T - A),
-k = 128, p = 16, FP32 blocks.
+inside the call.  Default workload: Chung-Lu power-law graph, n = 2,000,000,
+exponent 2.3, mean degree 25, M = (1/5) sum_{j=1..5} T^j - 0.05 (11^T - A),
+k = 256, p = 32.  `value` is the time per step with FP32 blocks; the same
+line carries the BF16-storage form (BF16 blocks with an FP32 finish) over a
+fixed number of steps, and the singular-value errors and subspace angles of
+both against an FP64 run of the library from the same start block at a
+fixed q = 2.
 
-Prints one JSON line.  `roofline` describes the sparse-pass kernel (the
-kernel that bounds every product): algorithmic bytes (every gathered row
-counted each time it is gathered) over the summed HIP-event durations of
-all its launches in the timed region.  `cpu_baseline` times the FP64 CPU
-oracle on a bounded sample of the same workload (one sparse product and
-one Householder QR at full size) and scales it to one whole iSVD.
+`roofline` describes the sparse-pass kernel (the kernel that bounds every
+product) over the FP32 passes of the timed steps: algorithmic bytes (every
+gathered row counted each time it is gathered) over the summed HIP-event
+durations of its launches; `traffic` is the measured bytes per launch from
+hardware counters when they were taken on the current source.
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload and scales it to one whole iSVD (extrapolated; see its `sample`).
+Other modes: --config c2|c3|c5, --peaks, --products, --traffic-from,
+--learners, --dag, --ablation.
 """
 
 from __future__ import annotations
@@ -36,7 +43,24 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c4", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--bf16-steps", type=int, default=5,
+                    help="default workload: timed BF16-storage steps (after one warm-up)")
+    ap.add_argument("--error-q", type=int, default=2,
+                    help="default workload: power iterations of the FP64 / FP32 / BF16 error runs")
+    ap.add_argument("--no-errors", action="store_true")
+    ap.add_argument("--peaks", action="store_true",
+                    help="measure the device's peak rates instead: streaming copy (HBM), repeated reads of a "
+                         "96 MiB buffer (Infinity Cache), FP64 and FP32 MFMA; one JSON line")
+    ap.add_argument("--products", type=int, default=0,
+                    help="time this many product pairs (M Y, M^T Y) per block storage (FP32, BF16) on the "
+                         "workload's operator instead of whole SVDs (a short run for hardware counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="summarise two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--products --calibrate-copy run into profiles/spmm_traffic_<workload>.json (no GPU)")
+    ap.add_argument("--oracle-runs", type=int, default=1,
+                    help="--config c2/c3: timed runs of the FP64 oracle at fixed q on the GPU's start block "
+                         "(median reported; 0 skips it)")
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16"])
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=2000)
@@ -46,7 +70,8 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 1 GiB device buffer 3 times (a plain copy kernel of known size, "
                          "to scale hardware byte counters)")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "spmm_traffic.json"))
+    ap.add_argument("--traffic-json", default=None,
+                    help="counter summary to read `traffic` from (default profiles/spmm_traffic_<workload>.json)")
     ap.add_argument("--warmstart", default=None,
                     help="trained warm-start parameters (.npy); each step then computes the features, the "
                          "network's start block and the iSVD from it, and the same steps with a Gaussian "
@@ -279,60 +304,408 @@ def learners_bench(args, lib, torch, np):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(g, cfg, applies, orths):
-    """Oracle timing on a bounded sample: one sparse product T @ P and one
-    Householder QR of an n x l block, both FP64 at full size, scaled to the
-    products and orthonormalisations of one GPU run.  Feature form: one
-    product with M and one with M^T by the oracle's operator (materialised
-    blocks A_hat^j X) instead of the sparse product."""
-    import numpy as np
+
+def host_info():
+    """Host cores and CPU model of the machine the oracle runs on."""
     from threadpoolctl import threadpool_info
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"nproc": nproc, "blas_threads": blas, "cpu_model": model}
+
+
+def infinity_cache_peak():
+    """Infinity-Cache read rate measured by `bench.py --peaks` (GB/s), from
+    the peaks record in profiles/, else the HBM figure."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "peaks_mi355x.json")) as fh:
+            return float(json.load(fh)["config"]["infinity_cache_read_gbps"])
+    except (OSError, ValueError, KeyError):
+        return HBM_PEAK_GBPS
+
+
+def traffic_path(args, workload):
+    return args.traffic_json or os.path.join(ROOT, "profiles", f"spmm_traffic_{workload}.json")
+
+
+def spmm_source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2111_06312_amd", "csrc", "spmm.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def load_traffic(args, workload, storage):
+    """Measured bytes per sparse pass over `storage` blocks, or None when no
+    counter summary exists for this workload or it was taken on another
+    version of the kernel's source."""
+    path = traffic_path(args, workload)
+    try:
+        with open(path) as fh:
+            tj = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if tj.get("workload") != workload or tj.get("spmm_source_sha256_16") != spmm_source_hash():
+        return None
+    rec = tj.get("passes", {}).get(storage)
+    return None if rec is None else rec.get("bytes_per_launch")
+
+
+def pass_roofline(lib, storage, peak_gbps, bound, args, workload, steps_s):
+    """Roofline object of the sparse passes over `storage` blocks recorded
+    since profiling was enabled (the record is kept)."""
+    ms, gather_b, comp_b, launches = lib.profile_spmm_read_storage(storage)
+    if launches == 0:
+        return None
+    avg_s = ms / 1e3 / launches
+    achieved = gather_b / launches / avg_s / 1e9
+    name = {lib.FP32: "fp32", lib.BF16: "bf16", lib.FP64: "fp64"}[storage]
+    traffic = load_traffic(args, workload, name)
+    out = {"bound": bound, "achieved": round(achieved, 1), "peak": peak_gbps, "unit": "GB/s",
+           "frac": round(achieved / peak_gbps, 4), "traffic": traffic,
+           "kernel": "spmm_pass_kernel", "storage": name, "avg_launch_us": round(avg_s * 1e6, 2),
+           "launches": launches, "bytes_per_launch": round(gather_b / launches),
+           "compulsory_bytes_per_launch": round(comp_b / launches),
+           "compulsory_gbps": round(comp_b / launches / avg_s / 1e9, 1),
+           "share_of_steps": round(ms / 1e3 / steps_s, 4) if steps_s > 0 else None}
+    if traffic:
+        out["traffic_gbps"] = round(traffic / avg_s / 1e9, 1)
+        out["traffic_frac"] = round(traffic / avg_s / 1e9 / peak_gbps, 4)
+    return out
+
+
+def subspace_angle(torch, Ua, Ub, k):
+    """Largest principal angle (rad) between span(Ua[:, :k]) and span(Ub[:, :k])
+    (device tensors; FP64 arithmetic): asin of the 2-norm of the part of Ub
+    outside span(Ua), Ua orthonormal."""
+    A = Ua[:, :k].double()
+    B = Ub[:, :k].double()
+    R = B - A @ (A.T @ B)
+    w = torch.linalg.eigvalsh(R.T @ R)
+    s = float(torch.sqrt(torch.clamp(w[-1], min=0.0)))
+    import math
+    return math.asin(min(s, 1.0))
+
+
+def gapped_k(S, k, rel_gap=1e-3):
+    """Largest k' <= k whose Ritz gap (s_k' - s_k'+1) / s_k' reaches rel_gap."""
+    for kk in range(k, 0, -1):
+        if kk == len(S) or (S[kk - 1] - S[kk]) / S[kk - 1] >= rel_gap:
+            return kk
+    return 1
+
+
+def cpu_baseline_extrapolated(g, cfg, applies, orths, row_frac=1 / 16):
+    """Oracle timing on a bounded sample of a large NE workload: one FP64 sparse
+    product T[rows] @ P over a random sample of the rows (scaled by the nnz
+    ratio) and one LAPACK Householder QR of a row sample of an n x l block
+    (scaled linearly in the rows), scaled to the products and
+    orthonormalisations of one GPU step."""
+    import numpy as np
 
     from oracle.graph import adjacency, transition
     from oracle.isvd import orthonorm_qr
 
-    if cfg.form == "featprop":
-        from oracle.operators import FeatPropDesignMatrix
-        from synth import block_features
-        x = block_features(g.blocks, cfg.d, seed=1000 + cfg.index)
-        m = FeatPropDesignMatrix.from_graph(g, x, cfg.L)
-        rng = np.random.default_rng(0)
-        gm = rng.standard_normal((m.shape[1], cfg.l))
-        p = rng.standard_normal((g.n, cfg.l))
-        t0 = time.perf_counter()
-        _ = m.dot(gm)
-        _ = m.T.dot(p)
-        t_pair = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        _ = orthonorm_qr(p)
-        t_qr = time.perf_counter() - t0
-        total = applies / 2 * t_pair + orths * t_qr
-        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-        return {
-            "value": round(total, 3), "unit": "s", "cores": blas_threads, "kind": "oracle",
-            "sample": (f"one FP64 product pair M G, M^T P of the oracle's feature operator ({t_pair:.2f} s) and "
-                       f"one LAPACK QR of {g.n}x{cfg.l} ({t_qr:.2f} s, {blas_threads} BLAS threads) at full "
-                       f"size, scaled by {applies} products and {orths} QRs of the GPU run"),
-        }
-
+    rng = np.random.default_rng(0)
     a = adjacency(g.n, g.indptr, g.indices, add_self_loops=cfg.self_loops)
     t = transition(a)
-    p = np.random.default_rng(0).standard_normal((g.n, cfg.l))
+    rows = np.sort(rng.choice(g.n, max(1, int(g.n * row_frac)), replace=False))
+    ts = t[rows]
+    p = rng.standard_normal((g.n, cfg.l))
     t0 = time.perf_counter()
-    _ = t @ p
-    t_pass = time.perf_counter() - t0
+    _ = ts @ p
+    t_pass = (time.perf_counter() - t0) * t.nnz / max(ts.nnz, 1)
+    nq = max(cfg.l, int(g.n * row_frac))
     t0 = time.perf_counter()
-    _ = orthonorm_qr(p)
-    t_qr = time.perf_counter() - t0
+    _ = orthonorm_qr(p[:nq])
+    t_qr = (time.perf_counter() - t0) * g.n / nq
     passes_per_apply = cfg.K + 1          # K powers of T plus the A product of the lambda term
     total = applies * passes_per_apply * t_pass + orths * t_qr
-    blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    h = host_info()
     return {
-        "value": round(total, 3), "unit": "s", "cores": blas_threads, "kind": "oracle",
-        "sample": (f"one FP64 scipy CSR product T@P ({t_pass:.2f} s, single-threaded) and one LAPACK QR of "
-                   f"{g.n}x{cfg.l} ({t_qr:.2f} s, {blas_threads} BLAS threads) at full size, scaled by "
-                   f"{applies} products x {passes_per_apply} sparse passes and {orths} QRs of the GPU run"),
+        "value": round(total, 2), "unit": "s", "cores": h["nproc"], "kind": "oracle", "extrapolated": True,
+        "cpu_model": h["cpu_model"], "blas_threads": h["blas_threads"],
+        "sample": (f"extrapolated: one FP64 scipy CSR product T[rows] @ P over {len(rows)} sampled rows "
+                   f"({ts.nnz} of {t.nnz} stored entries, scaled to {t_pass:.2f} s for the whole T, "
+                   f"single-threaded) and one LAPACK QR of {nq} x {cfg.l} (scaled to {t_qr:.2f} s for "
+                   f"{g.n} rows, {h['blas_threads']} BLAS threads), scaled by {applies} products x "
+                   f"{passes_per_apply} sparse passes and {orths} QRs of the GPU step"),
     }
+
+
+def oracle_timed(g, cfg, omega_np, x=None, runs=1):
+    """The FP64 oracle's Algorithm 1 at fixed q on the given start block (the
+    GPU run's, as FP64), whole: every product, Householder QR and the final
+    SVD.  Median wall time of `runs` runs and the oracle's singular values
+    and left basis."""
+    from oracle.isvd import isvd as oracle_isvd
+    from oracle.operators import FeatPropDesignMatrix, NEDesignMatrix
+    if cfg.form == "featprop":
+        m = FeatPropDesignMatrix.from_graph(g, x, cfg.L)
+    else:
+        m = NEDesignMatrix.from_graph(g, cfg.coeffs, cfg.lam, add_self_loops=cfg.self_loops)
+    times, out = [], None
+    for _ in range(max(1, runs)):
+        t0 = time.perf_counter()
+        out = oracle_isvd(m, cfg.k, omega_np, cfg.q)
+        times.append(time.perf_counter() - t0)
+    return statistics.median(times), out
+
+
+def peaks_bench(args, lib, torch):
+    """Peak rates of this GPU for the rooflines (library kernels, HIP events)."""
+    res = {}
+    nb = 4 << 30                                  # 4 GiB copy: far beyond every cache
+    src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    lib.peak_copy(src, dst, 1)
+    ms = lib.peak_copy(src, dst, 5)
+    res["hbm_copy_gbps"] = round(2 * 5 * nb / (ms / 1e3) / 1e9, 1)
+    res["hbm_copy"] = f"5 copies of {nb >> 20} MiB, read + write bytes counted"
+    rd_ms = lib.peak_read(src, 5)
+    res["hbm_read_gbps"] = round(5 * nb / (rd_ms / 1e3) / 1e9, 1)
+    del src, dst
+    ic = 96 << 20                                 # > 8 x 4 MB of L2, < 256 MB Infinity Cache
+    buf = torch.ones(ic // 4, dtype=torch.float32, device="cuda")
+    lib.peak_read(buf, 5)
+    reps = 200
+    ms = lib.peak_read(buf, reps)
+    res["infinity_cache_read_gbps"] = round(reps * ic / (ms / 1e3) / 1e9, 1)
+    res["infinity_cache_read"] = f"{reps} passes over {ic >> 20} MiB in one launch"
+    del buf
+    for name, prec, iters in (("fp64", lib.FP64, 20000), ("fp32", lib.FP32, 20000)):
+        lib.peak_mfma(prec, 100)
+        fl, ms = lib.peak_mfma(prec, iters)
+        res[f"mfma_{name}_tflops"] = round(fl / (ms / 1e3) / 1e12, 1)
+    res["device"] = torch.cuda.get_device_name(0)
+    line = {"metric": "device peak rates (roofline denominators)", "value": res["hbm_copy_gbps"],
+            "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": "peaks", **res},
+            "datasheet": {"hbm_gbps": HBM_PEAK_GBPS, "mfma_fp64_tflops": 78.6, "mfma_fp32_tflops": 157.3}}
+    print(json.dumps(line), flush=True)
+
+
+def products_bench(args, lib, torch, np):
+    """`--products` pairs (M Y then M^T Y) per block storage on the workload's
+    operator, after one warm-up pair; one JSON line with the sparse-pass
+    rates.  Short enough to run under hardware counters."""
+    from synth import CONFIGS
+    from synth.configs import make_graph
+    cfg = CONFIGS[args.config]
+    g = make_graph(cfg)
+    storages = [("fp32", lib.FP32)] + ([("bf16", lib.BF16)] if cfg.form == "ne" else [])
+    res = {}
+    for name, prec in storages:
+        if cfg.form == "featprop":
+            from synth import block_features
+            X = torch.as_tensor(block_features(g.blocks, cfg.d, seed=1000 + cfg.index)).cuda()
+            op = lib.Operator(g, form="featprop", X=X, L=cfg.L, precision=prec)
+        else:
+            op = lib.Operator(g, form="ne", coeffs=cfg.coeffs, lam=cfg.lam, self_loops=cfg.self_loops,
+                              precision=prec)
+        y = lib.gaussian_block(op.shape[1], cfg.l, seed=1, dtype=op.dtype)
+        op.matmul(op.matmul(y), transpose=True)
+        torch.cuda.synchronize()
+        print(f"[bench] products {name}: {args.products} pairs", file=sys.stderr, flush=True)
+        lib.profile_spmm(True)
+        t0 = time.perf_counter()
+        for _ in range(args.products):
+            op.matmul(op.matmul(y), transpose=True)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.products
+        ms, gb, cb, launches = lib.profile_spmm_read()
+        lib.profile_spmm(False)
+        res[name] = {"pair_ms": round(1e3 * wall, 3), "passes": launches,
+                     "avg_pass_us": round(1e3 * ms / max(launches, 1), 2),
+                     "bytes_per_launch": round(gb / max(launches, 1)),
+                     "gather_gbps": round(gb / (ms / 1e3) / 1e9, 1) if ms > 0 else None}
+        print(f"[bench] products {name}: {res[name]}", file=sys.stderr, flush=True)
+        op.close()
+        del y
+    line = {"metric": "sparse-pass rate over product pairs", "value": res["fp32"]["gather_gbps"], "unit": "GB/s",
+            "n_gpus": 1, "steps": args.products, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": cfg.name, "n": g.n, "nnz": int(g.nnz), "l": cfg.l, **res}}
+    print(json.dumps(line), flush=True)
+
+
+def traffic_summary(args):
+    """Counter files of a `--products N --calibrate-copy` run -> measured bytes
+    per sparse pass, per block storage.  The copy kernel's dispatches (known
+    bytes) scale each counter to bytes."""
+    import csv
+    from synth import CONFIGS
+    cfg = CONFIGS[args.config]
+
+    def per_dispatch(path, counter):
+        vals = {}
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                key = (row.get("Dispatch_Id") or row.get("Correlation_Id"), row["Kernel_Name"])
+                vals[key] = vals.get(key, 0.0) + float(row["Counter_Value"])
+        return vals
+
+    def split(vals):
+        out = {"copy": [], "fp32": [], "bf16": [], "fp64": []}
+        for (_, kname), v in vals.items():
+            if "peak_copy_kernel" in kname:
+                out["copy"].append(v)
+            elif "spmm_pass_kernel<isvd::bf16" in kname:
+                out["bf16"].append(v)
+            elif "spmm_pass_kernel<float" in kname:
+                out["fp32"].append(v)
+            elif "spmm_pass_kernel<double" in kname:
+                out["fp64"].append(v)
+        return out
+
+    fetch = split(per_dispatch(args.traffic_from[0], "FETCH_SIZE"))
+    write = split(per_dispatch(args.traffic_from[1], "WRITE_SIZE"))
+    copy_bytes = 1 << 30
+    assert fetch["copy"] and write["copy"], "no copy-kernel dispatches: run with --calibrate-copy"
+    f_scale = copy_bytes / (statistics.median(fetch["copy"]) * 1024.0)
+    w_scale = copy_bytes / (statistics.median(write["copy"]) * 1024.0)
+    passes = {}
+    for name in ("fp32", "bf16", "fp64"):
+        if not fetch[name]:
+            continue
+        fk = statistics.mean(fetch[name])
+        wk = statistics.mean(write[name]) if write[name] else 0.0
+        passes[name] = {"fetch_size_kib_per_dispatch": round(fk, 1), "write_size_kib_per_dispatch": round(wk, 1),
+                        "dispatches": len(fetch[name]),
+                        "bytes_per_launch": round(fk * 1024.0 * f_scale + wk * 1024.0 * w_scale)}
+    out = {"workload": cfg.name, "kernel": "spmm_pass_kernel", "spmm_source_sha256_16": spmm_source_hash(),
+           "calibration": f"copy kernel of {copy_bytes} bytes: FETCH_SIZE x {f_scale:.5f}, WRITE_SIZE x {w_scale:.5f}",
+           "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5), "passes": passes}
+    path = traffic_path(args, cfg.name)
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(out))
+
+
+def headline(args, lib, torch, np):
+    """The default line: the n = 2,000,000 NE workload with FP32 blocks to
+    rho <= tol (`value`), the BF16-storage form beside it, and the errors of
+    both against an FP64 run from the same start block at fixed q."""
+    from synth import CONFIGS
+    from synth.configs import make_graph
+    cfg = CONFIGS["c4"]
+    t0 = time.perf_counter()
+    g = make_graph(cfg)
+    print(f"[bench] graph {cfg.name}: n={g.n} nnz={g.nnz} ({time.perf_counter() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    kw = dict(tol=args.tol, max_iter=args.max_iter, check_every=args.check_every)
+    mk = lambda prec: lib.Operator(g, form="ne", coeffs=cfg.coeffs, lam=cfg.lam, self_loops=cfg.self_loops,
+                                   precision=prec)
+    op32 = mk(lib.FP32)
+    for w in range(args.warmup):
+        _, _, _, info = op32.truncated_svd(cfg.k, cfg.p, seed=1000 + w, allow_not_converged=True, **kw)
+        print(f"[bench] warmup {w}: {info.seconds:.3f} s, iterations {info.iterations}, rho {info.residual:.2e}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    lib.profile_spmm(True)
+    times, infos = [], []
+    t_start = time.perf_counter()
+    for s_ in range(args.steps):
+        ts = time.perf_counter()
+        _, _, _, info = op32.truncated_svd(cfg.k, cfg.p, seed=s_, allow_not_converged=True, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        infos.append(info)
+        print(f"[bench] step {s_}: {times[-1]:.3f} s, iterations {info.iterations}, applies {info.applies}, "
+              f"rho {info.residual:.2e}, status {info.status}, ritz {info.ritz_steps}, fallback {info.used_fallback}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    roof32 = pass_roofline(lib, lib.FP32, HBM_PEAK_GBPS, "hbm", args, cfg.name, total)
+    lib.profile_spmm_read()
+    lib.profile_spmm(False)
+
+    # BF16 storage with the FP32 finish, same tolerance
+    op16 = mk(lib.BF16)
+    kw16 = dict(kw, fp32_switch_tol=args.fp32_switch_tol)
+    op16.truncated_svd(cfg.k, cfg.p, seed=2000, allow_not_converged=True, **kw16)
+    torch.cuda.synchronize()
+    lib.profile_spmm(True)
+    t16, i16 = [], []
+    tb = time.perf_counter()
+    for s_ in range(args.bf16_steps):
+        ts = time.perf_counter()
+        _, _, _, info = op16.truncated_svd(cfg.k, cfg.p, seed=s_, allow_not_converged=True, **kw16)
+        torch.cuda.synchronize()
+        t16.append(time.perf_counter() - ts)
+        i16.append(info)
+        print(f"[bench] bf16 step {s_}: {t16[-1]:.3f} s, iterations {info.iterations} "
+              f"({info.bf16_iterations} in BF16), rho {info.residual:.2e}, status {info.status}",
+              file=sys.stderr, flush=True)
+    total16 = time.perf_counter() - tb
+    roof16 = pass_roofline(lib, lib.BF16, HBM_PEAK_GBPS, "hbm", args, cfg.name, total16)
+    roof16_f = pass_roofline(lib, lib.FP32, HBM_PEAK_GBPS, "hbm", args, cfg.name, total16)
+    lib.profile_spmm_read()
+    lib.profile_spmm(False)
+    mean32 = sum(times) / len(times)
+    mean16 = sum(t16) / len(t16) if t16 else None
+    bf16 = {"steps": len(t16), "mean_step_s": round(mean16, 4) if mean16 else None,
+            "speedup_vs_fp32": round(mean32 / mean16, 3) if mean16 else None,
+            "iterations": [i.iterations for i in i16], "bf16_iterations": [i.bf16_iterations for i in i16],
+            "residual": [i.residual for i in i16], "converged": all(i.status == 0 for i in i16),
+            "roofline_bf16_passes": roof16, "roofline_fp32_finish_passes": roof16_f}
+
+    errors = None
+    if not args.no_errors:
+        # the same start block for all three: FP64 Philox draws, rounded to each storage
+        q = args.error_q
+        om = lib.gaussian_block(g.n, cfg.l, seed=cfg.omega_seed, dtype=torch.float64)
+        op64 = mk(lib.FP64)
+        te = time.perf_counter()
+        U64, S64, _, _ = op64.truncated_svd(cfg.k, cfg.p, q=q, omega=om)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - te
+        op64.close()
+        del op64
+        s64 = S64.cpu().numpy()
+        kk = gapped_k(s64, cfg.k)
+        errors = {"q": q, "start_block": f"Philox N(0,1) seed {cfg.omega_seed}, FP64, rounded per storage",
+                  "fp64_s": round(t64, 3), "k_gapped": kk}
+        for name, op, dt in (("fp32", op32, torch.float32), ("bf16", op16, torch.bfloat16)):
+            U, S, _, _ = op.truncated_svd(cfg.k, cfg.p, q=q, omega=om.to(dt))
+            s = S.cpu().numpy()
+            errors[name] = {"sigma_max_rel_err": float(np.max(np.abs(s - s64) / s64)),
+                            "subspace_angle_rad": subspace_angle(torch, U64, U, kk)}
+            del U
+            print(f"[bench] error run {name}: {errors[name]}", file=sys.stderr, flush=True)
+        del U64, om
+    op16.close()
+
+    converged = all(i.status == 0 for i in infos)
+    line = {
+        "metric": "rank-k iSVD wall time at rel. residual 1e-4; SpMM achieved HBM GB/s vs peak",
+        "value": round(total / args.steps, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * total / args.steps, 2), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": cfg.name, "n": g.n, "nnz": int(g.nnz), "k": cfg.k, "p": cfg.p, "K": cfg.K,
+                   "lambda": cfg.lam, "tol": args.tol, "csr": "int64 offsets, int32 column ids, unit values "
+                   "(A is 0/1; D^-1 applied as an FP32 row scale)",
+                   "iterations": [i.iterations for i in infos], "applies": [i.applies for i in infos],
+                   "residual": [i.residual for i in infos], "converged": converged,
+                   "median_step_s": round(statistics.median(times), 4), "start_block": "gaussian",
+                   "bf16_storage": bf16, "errors_vs_fp64": errors},
+        "roofline": roof32,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        last = infos[-1]
+        line["cpu_baseline"] = cpu_baseline_extrapolated(g, cfg, last.applies, last.applies)
+    op32.close()
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -342,6 +715,9 @@ def main():
               "the multi-GPU sharding of this path is a design note, not a measured configuration.",
               file=sys.stderr)
         sys.exit(2)
+    if args.traffic_from:
+        traffic_summary(args)
+        return
     import numpy as np
     import torch
 
@@ -351,14 +727,18 @@ def main():
 
     lib.load()
     if args.calibrate_copy:
-        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print("[bench] calibration copies: 3 x 1 GiB device-to-device", file=sys.stderr, flush=True)
+        lib.peak_copy(src, dst, 3)
+        print("[bench] calibration copies: 3 x 1 GiB by the library's copy kernel", file=sys.stderr, flush=True)
         del src, dst
+    if args.peaks:
+        peaks_bench(args, lib, torch)
+        return
+    if args.products:
+        products_bench(args, lib, torch, np)
+        return
     if args.learners:
         learners_bench(args, lib, torch, np)
         return
@@ -368,6 +748,9 @@ def main():
     if args.ablation:
         ablation_bench(args, lib, torch, np)
         return
+    if args.config == "c4" and args.precision is None and not args.warmstart:
+        headline(args, lib, torch, np)
+        return
     cfg = CONFIGS[args.config]
     prec_name = args.precision or ("bf16" if cfg.precision == "bf16" else "fp32")
     precision = lib.BF16 if prec_name == "bf16" else lib.FP32
@@ -375,9 +758,11 @@ def main():
     g = make_graph(cfg)
     print(f"[bench] graph {cfg.name}: n={g.n} nnz={g.nnz} ({time.perf_counter() - t0:.1f} s)",
           file=sys.stderr, flush=True)
+    X = x_np = None
     if cfg.form == "featprop":
         from synth import block_features
-        X = torch.as_tensor(block_features(g.blocks, cfg.d, seed=1000 + cfg.index)).cuda()
+        x_np = block_features(g.blocks, cfg.d, seed=1000 + cfg.index)
+        X = torch.as_tensor(x_np).cuda()
         op = lib.Operator(g, form="featprop", X=X, L=cfg.L, precision=precision)
     else:
         op = lib.Operator(g, form="ne", coeffs=cfg.coeffs, lam=cfg.lam, self_loops=cfg.self_loops,
@@ -386,7 +771,6 @@ def main():
               fp32_switch_tol=args.fp32_switch_tol if precision == lib.BF16 else 0.0)
     ws = None
     if args.warmstart:
-        import numpy as np
         ws = lib.WarmStart(cfg.k, seed=0)
         ws.set_params(np.load(args.warmstart))
 
@@ -435,27 +819,18 @@ def main():
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
-    spmm_ms, gather_b, comp_b, launches = lib.profile_spmm_read()
+    # blocks of n x l beyond the 256 MB Infinity Cache: rows come from HBM
+    block_bytes = g.n * cfg.l * (2 if precision == lib.BF16 else 4)
+    in_cache = block_bytes < 200e6
+    peak = HBM_PEAK_GBPS
+    bound = "hbm"
+    if in_cache:
+        bound = "infinity-cache"
+        peak = infinity_cache_peak()
+    roof = pass_roofline(lib, precision, peak, bound, args, cfg.name, total)
+    lib.profile_spmm_read()
     lib.profile_spmm(False)
     ms_per_step = 1e3 * total / args.steps
-    avg_launch_s = spmm_ms / 1e3 / max(launches, 1)
-    achieved = gather_b / max(launches, 1) / avg_launch_s / 1e9
-    compulsory = comp_b / max(launches, 1) / avg_launch_s / 1e9
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            with open(args.traffic_json) as fh:
-                tj = json.load(fh)
-            import hashlib
-            src = os.path.join(ROOT, "paper_2111_06312_amd", "csrc", "spmm.hip")
-            with open(src, "rb") as fh:
-                cur = hashlib.sha256(fh.read()).hexdigest()[:16]
-            # counters describe the kernel they were taken on: stale once its source changed
-            if (tj.get("workload") == cfg.name and tj.get("precision") == prec_name
-                    and tj.get("spmm_source_sha256_16") == cur):
-                traffic = tj.get("bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = None
     converged = all(i.status == 0 for i in infos)
     line = {
         "metric": "rank-k iSVD wall time at rel. residual 1e-4; SpMM achieved HBM GB/s vs peak",
@@ -480,18 +855,41 @@ def main():
                    "start_block": "learned warm start" if ws is not None else "gaussian",
                    **({"gaussian_start": gauss, "warmstart_fallbacks": fallbacks,
                        "warmstart_weights": os.path.relpath(args.warmstart, ROOT)} if ws is not None else {})},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                     "kernel": "spmm_pass_kernel", "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                     "launches": launches, "bytes_per_launch": round(gather_b / max(launches, 1)),
-                     "compulsory_gbps": round(compulsory, 1),
-                     "spmm_share_of_step": round(spmm_ms / 1e3 / total, 4)},
+        "roofline": roof,
     }
-    if not args.no_cpu_baseline and cfg.n <= 500_000:
+    if not args.no_cpu_baseline and args.config in ("c2", "c3") and args.oracle_runs > 0 and ws is None:
+        # the oracle run whole (Algorithm 1, Householder QR) at fixed q on the start block of a
+        # fixed-q GPU run, both timed; errors of the GPU result against it
+        om = lib.gaussian_block(op.shape[1], cfg.l, seed=cfg.omega_seed, dtype=torch.float64)
+        om_np = om.cpu().numpy()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        U, S, _, ginfo = op.truncated_svd(cfg.k, cfg.p, q=cfg.q, omega=om.to(op.dtype))
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - tg
+        print(f"[bench] timing the CPU oracle: {args.oracle_runs} run(s) at q = {cfg.q}", file=sys.stderr,
+              flush=True)
+        t_or, (uo, so, _) = oracle_timed(g, cfg, om_np, x=x_np, runs=args.oracle_runs)
+        s = S.cpu().numpy()
+        kk = gapped_k(so, cfg.k)
+        h = host_info()
+        line["cpu_baseline"] = {
+            "value": round(t_or, 2), "unit": "s", "cores": h["nproc"], "kind": "oracle", "extrapolated": False,
+            "cpu_model": h["cpu_model"], "blas_threads": h["blas_threads"],
+            "sample": (f"the whole FP64 oracle (Algorithm 1 with Householder QR, LAPACK SVD) at fixed q = {cfg.q} "
+                       f"on the start block of a fixed-q GPU run (Philox seed {cfg.omega_seed}), median of "
+                       f"{args.oracle_runs}; the GPU's tolerance-mode steps run about "
+                       f"{infos[-1].iterations / max(cfg.q, 1):.0f} times as many iterations"),
+            "gpu_fixed_q_s": round(tg, 4),
+            "speedup_fixed_q": round(t_or / tg, 1),
+            "sigma_max_rel_err": float(np.max(np.abs(s - so) / so)),
+            "subspace_angle_rad": subspace_angle(torch, torch.as_tensor(uo, device="cuda"), U, kk),
+            "k_gapped": kk,
+        }
+    elif not args.no_cpu_baseline and cfg.form == "ne":
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         last = infos[-1]
-        # the oracle orthonormalises every product once (Householder QR)
-        line["cpu_baseline"] = cpu_baseline(g, cfg, last.applies, last.applies)
+        line["cpu_baseline"] = cpu_baseline_extrapolated(g, cfg, last.applies, last.applies)
     op.close()
     print(json.dumps(line), flush=True)
 

@@ -385,12 +385,37 @@ isvd_status isvd_profile_spmm_enable(int on);
 isvd_status isvd_profile_spmm_read(double* total_ms, double* gather_bytes, double* compulsory_bytes,
                                    int64_t* launches);
 
+/* The same totals restricted to the passes whose blocks are stored in
+ * `storage` (a BF16-storage SVD also runs FP32 passes in its finishing
+ * phase).  Waits for the recorded events; keeps the record (the next
+ * isvd_profile_spmm_read or enable clears it).  Errors: ISVD_E_INVALID. */
+isvd_status isvd_profile_spmm_read_storage(isvd_precision storage, double* total_ms, double* gather_bytes,
+                                           double* compulsory_bytes, int64_t* launches);
+
 /* Totals of the learner calls recorded since the last enable/read (host
  * arrays of 3: [0] isvd_ne_embeddings, [1] isvd_ne_scores, [2] isvd_nc_fit
  * from its first kernel to its last): summed event durations in ms,
  * algorithmic bytes (U, V, Y rows read once per use, outputs written once,
  * indices), number of calls.  Waits for the events; clears the records. */
 isvd_status isvd_profile_learners_read(double* ms, double* bytes, int64_t* launches);
+
+/* Peak rates of the device, for the rooflines of the kernels above (not
+ * steps of the method).  Each call enqueues its kernels between a hipEvent
+ * pair on `stream`, waits, and returns the elapsed time in *ms.
+ *  isvd_peak_copy: `reps` streaming copies of `bytes` (a positive multiple of
+ *    16; both device buffers 16-byte aligned) from src to dst; HBM rate =
+ *    2 reps bytes / time.
+ *  isvd_peak_read: one launch that reads the `bytes` of src `reps` times,
+ *    each pass starting a third of the buffer further on (no L2 reuse between
+ *    passes); a buffer larger than the L2s and smaller than the Infinity
+ *    Cache gives that cache's read rate = reps bytes / time.
+ *  isvd_peak_mfma: back-to-back independent MFMAs (16x16x4, FP64 or FP32 by
+ *    `precision`), `iters` rounds of eight per wave; *flops receives the
+ *    floating-point operations done.
+ * Allocate a small device sink per call.  Errors: ISVD_E_INVALID, ISVD_E_HIP. */
+isvd_status isvd_peak_copy(const void* src, void* dst, int64_t bytes, int reps, double* ms, void* stream);
+isvd_status isvd_peak_read(const void* src, int64_t bytes, int reps, double* ms, void* stream);
+isvd_status isvd_peak_mfma(isvd_precision precision, int64_t iters, double* flops, double* ms, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Learned warm start (not in the paper): a 16 -> 128 -> 128 -> k MLP with

@@ -17,6 +17,11 @@ template <typename T>
 void orthonormalize_block(int64_t rows, int cols, T* Y, int64_t ld, double* Rout, hipStream_t stream,
                           bool householder);
 
+double peak_copy(const void* src, void* dst, int64_t bytes, int reps, hipStream_t stream);
+double peak_read(const void* src, int64_t bytes, int reps, uint32_t* sink, hipStream_t stream);
+int64_t peak_sink_elems();
+double peak_mfma(bool fp64, int64_t iters, double* sink, double* flops, hipStream_t stream);
+
 namespace {
 thread_local std::string g_last_error;
 }
@@ -619,6 +624,57 @@ isvd_status isvd_profile_spmm_read(double* total_ms, double* gather_bytes, doubl
   return guarded([&]() -> isvd_status {
     ISVD_CHECK(total_ms && gather_bytes && compulsory_bytes && launches, ISVD_E_INVALID, "null argument");
     spmm_profile_read(total_ms, gather_bytes, compulsory_bytes, launches);
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_profile_spmm_read_storage(isvd_precision storage, double* total_ms, double* gather_bytes,
+                                           double* compulsory_bytes, int64_t* launches) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(total_ms && gather_bytes && compulsory_bytes && launches, ISVD_E_INVALID, "null argument");
+    int eb = 0;
+    switch (storage) {
+      case ISVD_FP64: eb = 8; break;
+      case ISVD_FP32: eb = 4; break;
+      case ISVD_BF16: eb = 2; break;
+      default: ISVD_CHECK(false, ISVD_E_INVALID, "unknown storage precision");
+    }
+    spmm_profile_read(total_ms, gather_bytes, compulsory_bytes, launches, eb, false);
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_peak_copy(const void* src, void* dst, int64_t bytes, int reps, double* ms, void* stream) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(src && dst && ms, ISVD_E_INVALID, "null argument");
+    ISVD_CHECK(bytes >= 16 && bytes % 16 == 0 && reps >= 1, ISVD_E_INVALID, "bytes: a positive multiple of 16");
+    ISVD_CHECK((reinterpret_cast<uintptr_t>(src) & 15u) == 0 && (reinterpret_cast<uintptr_t>(dst) & 15u) == 0,
+               ISVD_E_INVALID, "buffers must be 16-byte aligned");
+    *ms = peak_copy(src, dst, bytes, reps, static_cast<hipStream_t>(stream));
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_peak_read(const void* src, int64_t bytes, int reps, double* ms, void* stream) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(src && ms, ISVD_E_INVALID, "null argument");
+    ISVD_CHECK(bytes >= 16 && bytes % 16 == 0 && reps >= 1, ISVD_E_INVALID, "bytes: a positive multiple of 16");
+    ISVD_CHECK((reinterpret_cast<uintptr_t>(src) & 15u) == 0, ISVD_E_INVALID, "buffer must be 16-byte aligned");
+    DevBuf sink;
+    sink.ensure(static_cast<size_t>(peak_sink_elems()) * sizeof(uint32_t));
+    *ms = peak_read(src, bytes, reps, sink.as<uint32_t>(), static_cast<hipStream_t>(stream));
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_peak_mfma(isvd_precision precision, int64_t iters, double* flops, double* ms, void* stream) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(flops && ms, ISVD_E_INVALID, "null argument");
+    ISVD_CHECK(precision == ISVD_FP64 || precision == ISVD_FP32, ISVD_E_INVALID, "FP64 or FP32 only");
+    ISVD_CHECK(iters >= 1, ISVD_E_INVALID, "iters >= 1");
+    DevBuf sink;
+    sink.ensure(static_cast<size_t>(peak_sink_elems()) * sizeof(double));
+    *ms = peak_mfma(precision == ISVD_FP64, iters, sink.as<double>(), flops, static_cast<hipStream_t>(stream));
     return ISVD_OK;
   });
 }

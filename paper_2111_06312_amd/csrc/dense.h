@@ -48,11 +48,16 @@ __host__ __device__ inline int pad16(int l) { return (l + 15) / 16 * 16; }
 //   R64  : upper factor (lower triangle and padding set to the identity pattern)
 //   Rc   : R in compute type C (for the tall solve), Dinv_c: inverses of the
 //          16 x 16 diagonal tiles in compute type (lp/16 tiles, 256 entries each)
-//   flag : set to 1 on breakdown (pivot <= rel_tol * original diagonal or not finite)
-// `shift` is added to the diagonal before factorising.
+//   flag : three ints.  retry = 0: `shift` is added to the diagonal and
+//          flag[0] = 1 on breakdown (pivot <= rel_tol * original diagonal or
+//          not finite), else 0.  retry = 1: the repair launch, enqueued after
+//          every retry = 0 launch so that no host round trip is needed: it
+//          returns at once unless flag[0] is set, else factors G + s I with
+//          s = shift * tr(G) and no pivot threshold (shifted Cholesky QR),
+//          adds one to flag[2] and sets flag[1] if that fails as well.
 template <typename C>
 void launch_cholesky(int l, const double* G, int64_t ldg, double shift, double rel_tol, double* R64,
-                     C* Rc, C* Dinv_c, int* flag, hipStream_t stream);
+                     C* Rc, C* Dinv_c, int* flag, int retry, hipStream_t stream);
 
 // In place Y <- Y R^-1 (rows x l block, storage T, ld), R/Dinv from launch_cholesky.
 // colsum (optional, l doubles): FP64 column sums of the stored result, reduced

@@ -900,9 +900,16 @@ __device__ __forceinline__ void diag_tile_regs(const TileStore<kLds>& W, int J, 
 
 constexpr int kCholThreads = 512;
 
+// retry = 0: factor G + shift I; flag[0] = 1 on breakdown (pivot <= rel_tol x
+// its original diagonal, or not finite), else 0.
+// retry = 1 (the repair launch queued after every factorisation): nothing
+// unless flag[0] is set; then factor G + s I with s = shift x tr(G) and no
+// pivot threshold (shifted Cholesky QR), add one to flag[2] and set flag[1]
+// if this factorisation breaks down too or tr(G) is not positive and finite.
 template <typename C, bool kLds>
 __global__ __launch_bounds__(kCholThreads) void cholesky_kernel(int l, const double* G, int64_t ldg, double shift,
-                                                        double rel_tol, double* R64, C* Rc, C* Dc, int* flag) {
+                                                        double rel_tol, double* R64, C* Rc, C* Dc, int* flag,
+                                                        int retry) {
   extern __shared__ double chol_lds[];
   const int lp = pad16(l), T = lp / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
@@ -910,6 +917,29 @@ __global__ __launch_bounds__(kCholThreads) void cholesky_kernel(int l, const dou
   __shared__ double X[256];
   __shared__ double refd[kJacobiMaxNForChol];
   __shared__ int bad;
+  __shared__ double tr_part[kCholThreads / 64];
+  __shared__ double tr_shift;
+  __shared__ int skip, tr_bad;
+  if (retry) {
+    if (tid == 0) skip = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    __syncthreads();
+    if (skip) return;
+    double part = 0.0;
+    for (int i = tid; i < l; i += blockDim.x) part += G[static_cast<int64_t>(i) * ldg + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+    if (lane == 0) tr_part[wave] = part;
+    __syncthreads();
+    if (tid == 0) {
+      double tr = 0.0;
+      for (int w = 0; w < nw; ++w) tr += tr_part[w];
+      tr_bad = !(tr > 0.0 && isfinite(tr));
+      tr_shift = shift * tr;
+    }
+    __syncthreads();
+    shift = tr_shift;
+    rel_tol = 0.0;
+  }
   const TileStore<kLds> W{kLds ? chol_lds : R64, T, lp};
   for (int i = tid; i < lp; i += blockDim.x)
     refd[i] = i < l ? fabs(G[static_cast<int64_t>(i) * ldg + i] + shift) : 1.0;
@@ -1046,7 +1076,14 @@ __global__ __launch_bounds__(kCholThreads) void cholesky_kernel(int l, const dou
       }
     }
   }
-  if (tid == 0) *flag = bad;
+  if (tid == 0) {
+    if (retry) {
+      if (bad || tr_bad) flag[1] = 1;
+      flag[2] += 1;
+    } else {
+      flag[0] = bad;
+    }
+  }
 }
 
 // ============================================================ tall triangular solve
@@ -1962,19 +1999,19 @@ template void launch_gemm_tall<bf16>(int64_t, int, int, const bf16*, int64_t, in
 
 template <typename C>
 void launch_cholesky(int l, const double* G, int64_t ldg, double shift, double rel_tol, double* R64,
-                     C* Rc, C* Dinv_c, int* flag, hipStream_t stream) {
+                     C* Rc, C* Dinv_c, int* flag, int retry, hipStream_t stream) {
   const int T = pad16(l) / 16;
   const size_t lds = T <= kCholLdsMaxTiles ? static_cast<size_t>(T) * (T + 1) / 2 * 256 * sizeof(double) : 0;
   if (T <= kCholLdsMaxTiles)
     hipLaunchKernelGGL((cholesky_kernel<C, true>), dim3(1), dim3(kCholThreads), lds, stream, l, G, ldg, shift,
-                       rel_tol, R64, Rc, Dinv_c, flag);
+                       rel_tol, R64, Rc, Dinv_c, flag, retry);
   else
     hipLaunchKernelGGL((cholesky_kernel<C, false>), dim3(1), dim3(kCholThreads), 0, stream, l, G, ldg, shift,
-                       rel_tol, R64, Rc, Dinv_c, flag);
+                       rel_tol, R64, Rc, Dinv_c, flag, retry);
   ISVD_LAUNCH_CHECK();
 }
-template void launch_cholesky<double>(int, const double*, int64_t, double, double, double*, double*, double*, int*, hipStream_t);
-template void launch_cholesky<float>(int, const double*, int64_t, double, double, double*, float*, float*, int*, hipStream_t);
+template void launch_cholesky<double>(int, const double*, int64_t, double, double, double*, double*, double*, int*, int, hipStream_t);
+template void launch_cholesky<float>(int, const double*, int64_t, double, double, double*, float*, float*, int*, int, hipStream_t);
 
 template <typename T>
 void launch_trsm_tall(int64_t rows, int l, T* Y, int64_t ld, const typename ComputeOf<T>::type* Rc,

@@ -37,6 +37,8 @@ struct SvdState {
   bool householder = false;  // orthonormalise by Householder QR instead of Cholesky QR
   DevBuf hh_q, hh_work, hh_cs;
   int iterations = 0, applies = 0, bf16_iterations = 0, checks = 0, fallback = 0, ritz_steps = 0;
+  int repairs_seen = 0;    // shifted factorisations counted at the last read of the Cholesky flags
+  bool new_repairs = false;
   double residual = -1.0;
   bool have_ritz = false;
   bool zr_valid = false;   // ZR holds the right rotation of an earlier Ritz step of this call
@@ -46,7 +48,8 @@ struct SvdState {
   // residuals and Ritz values of the last check, Ritz values of the one before
   std::vector<double> rho_i, sig_k, prev_sig_k;
   void reset_counters() {
-    iterations = applies = bf16_iterations = checks = fallback = ritz_steps = 0;
+    iterations = applies = bf16_iterations = checks = fallback = ritz_steps = repairs_seen = 0;
+    new_repairs = false;
     residual = -1.0;
     have_ritz = false;
     zr_valid = false;
@@ -81,6 +84,23 @@ void trace_check(const SvdState& st, const char* phase, int t) {
                "| max rel dsig %.3e\n",
                phase, t, r[k - 1], r[k / 2], r[(9 * k) / 10], r[(99 * k) / 100], st.rho_i[0], st.rho_i[k - 1],
                st.sig_k[0], st.sig_k[k - 1], dsig);
+}
+
+// Cholesky flags (see launch_cholesky): zeroed once per call, read (with a
+// stream synchronisation) only where the host needs them.
+void clear_chol_flags(SvdState& st, hipStream_t stream) {
+  st.flag.ensure(4 * sizeof(int));
+  ISVD_HIP(hipMemsetAsync(st.flag.p, 0, 4 * sizeof(int), stream));
+}
+
+void read_chol_flags(SvdState& st, hipStream_t stream) {
+  int f[3] = {0, 0, 0};
+  ISVD_HIP(hipMemcpyAsync(f, st.flag.p, sizeof(f), hipMemcpyDeviceToHost, stream));
+  ISVD_HIP(hipStreamSynchronize(stream));
+  ISVD_CHECK(f[1] == 0, ISVD_E_NOT_SPD, "Cholesky breakdown: Gram matrix not positive definite even with a shift");
+  st.new_repairs = f[2] > st.repairs_seen;
+  if (f[2] > 0) st.fallback = 1;
+  st.repairs_seen = f[2];
 }
 
 // CholeskyQR2 of Y in place; Rout (optional) receives R2 R1; colsum (optional,
@@ -133,19 +153,28 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* cols
     st.Rcc.ensure(static_cast<size_t>(lp) * lp * sizeof(C));
     st.Dc.ensure(static_cast<size_t>(lp) * 16 * sizeof(C));
   }
-  auto factor = [&](double shift, double rel_tol, double* Rdst) {
-    if (use_inv)
-      launch_cholesky<double>(l, st.G.as<double>(), l, shift, rel_tol, Rdst, st.Rc64.as<double>(),
-                              st.Dc64.as<double>(), st.flag.as<int>(), stream);
-    else
-      launch_cholesky<C>(l, st.G.as<double>(), l, shift, rel_tol, Rdst, st.Rcc.as<C>(), st.Dc.as<C>(),
-                         st.flag.as<int>(), stream);
+  // Each factorisation is followed by its repair launch (shifted Cholesky QR,
+  // Fukaya et al.: G + s I with s = 11 (m l + l (l+1)) u tr(G)), which does
+  // nothing unless the first one broke down, so no pass waits for the host.
+  const double shift_coeff =
+      11.0 * (static_cast<double>(rows) * l + static_cast<double>(l) * (l + 1)) * 1.1102230246251565e-16;
+  auto factor = [&](double* Rdst) {
+    for (int retry = 0; retry < 2; ++retry) {
+      const double shift = retry ? shift_coeff : 0.0, rel_tol = retry ? 0.0 : 1e-14;
+      if (use_inv)
+        launch_cholesky<double>(l, st.G.as<double>(), l, shift, rel_tol, Rdst, st.Rc64.as<double>(),
+                                st.Dc64.as<double>(), st.flag.as<int>(), retry, stream);
+      else
+        launch_cholesky<C>(l, st.G.as<double>(), l, shift, rel_tol, Rdst, st.Rcc.as<C>(), st.Dc.as<C>(),
+                           st.flag.as<int>(), retry, stream);
+    }
   };
-  st.flag.ensure(4 * sizeof(int));
+  if (!st.flag.p) clear_chol_flags(st, stream);
   st.gram_work.ensure(gram_workspace_doubles(rows, l, l) * sizeof(double));
   double* Rp[2] = {st.R1.as<double>(), st.R2.as<double>()};
-  int passes = npass;
-  for (int pass = 0; pass < passes; ++pass) {
+  int done = 0;
+  auto run_pass = [&](bool want_colsum) {
+    const int pass = done++;
     double* Rdst = Rp[pass < 2 ? pass : 1];
     if (pass >= 2) {
       // a further pass: fold R2 into R1 first (R1 <- R2 R1)
@@ -155,32 +184,25 @@ void orthonormalize(SvdState& st, T* Y, int64_t rows, double* Rout, double* cols
                               hipMemcpyDeviceToDevice, stream));
     }
     launch_gram<T>(rows, l, l, Y, st.ld, Y, st.ld, true, st.G.as<double>(), l, st.gram_work.as<double>(), stream);
-    factor(0.0, 1e-14, Rdst);
-    int flag = 0;
-    ISVD_HIP(hipMemcpyAsync(&flag, st.flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
-    ISVD_HIP(hipStreamSynchronize(stream));
-    if (flag) {
-      // shifted Cholesky QR (Fukaya et al.): G + s I with s ~ 11 (m l + l (l+1)) u tr(G);
-      // the shifted pass is followed by two more
-      std::vector<double> g(static_cast<size_t>(l) * l);
-      double tr = 0.0;
-      ISVD_HIP(hipMemcpy(g.data(), st.G.p, g.size() * sizeof(double), hipMemcpyDeviceToHost));
-      for (int i = 0; i < l; ++i) tr += g[static_cast<size_t>(i) * l + i];
-      const double shift = 11.0 * (static_cast<double>(rows) * l + static_cast<double>(l) * (l + 1)) *
-                           1.1102230246251565e-16 * tr;
-      factor(shift, 0.0, Rdst);
-      ISVD_HIP(hipMemcpyAsync(&flag, st.flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
-      ISVD_HIP(hipStreamSynchronize(stream));
-      ISVD_CHECK(flag == 0 && tr > 0.0 && std::isfinite(tr), ISVD_E_NOT_SPD,
-                 "Cholesky breakdown: Gram matrix not positive definite even with a shift");
-      st.fallback = 1;
-      passes = pass + 3 > passes ? pass + 3 : passes;
+    factor(Rdst);
+    apply_rinv<T>(st, Y, rows, Rdst, use_inv, want_colsum ? colsum : nullptr, stream);
+  };
+  for (int pass = 0; pass < npass; ++pass) run_pass(pass + 1 == npass);
+  // A single pass only has to keep the span (its result feeds the next
+  // product), which the shifted factor does; its repairs are counted at the
+  // next read of the flags.  Bases that must be orthonormal (two passes) are
+  // checked here: after a repair, two more passes.
+  if (npass >= 2) {
+    for (int round = 0;; ++round) {
+      read_chol_flags(st, stream);
+      if (!st.new_repairs) break;
+      ISVD_CHECK(round < 2, ISVD_E_NOT_SPD, "Cholesky QR: Gram matrix still needs a shift after six passes");
+      run_pass(false);
+      run_pass(true);
     }
-    const bool last = pass + 1 == passes;
-    apply_rinv<T>(st, Y, rows, Rdst, use_inv, last ? colsum : nullptr, stream);
   }
   if (Rout) {
-    if (passes == 1) launch_convert<double, double>(lp, lp, st.R1.as<double>(), lp, Rout, lp, stream);
+    if (done == 1) launch_convert<double, double>(lp, lp, st.R1.as<double>(), lp, Rout, lp, stream);
     else launch_upper_mult(l, st.R2.as<double>(), st.R1.as<double>(), Rout, lp, stream);
   }
 }
@@ -227,7 +249,7 @@ double residual(SvdState& st, const T* Y, hipStream_t stream) {
   ISVD_HIP(hipMemcpyAsync(a.data(), st.left2.p, k * sizeof(double), hipMemcpyDeviceToHost, stream));
   ISVD_HIP(hipMemcpyAsync(b.data(), st.right2.p, k * sizeof(double), hipMemcpyDeviceToHost, stream));
   ISVD_HIP(hipMemcpyAsync(s.data(), st.sig.p, k * sizeof(double), hipMemcpyDeviceToHost, stream));
-  ISVD_HIP(hipStreamSynchronize(stream));
+  read_chol_flags(st, stream);   // the one synchronisation of a checked iteration
   double rho = 0.0;
   if (trace_on()) {
     st.prev_sig_k = st.sig_k;
@@ -553,12 +575,14 @@ isvd_status truncated_svd(isvd_operator* op, const isvd_svd_params* prm, void* U
   st.householder = prm->orth_method == 1;
   st.lp = pad16(st.l);
   st.ld = round_up(st.l, 8);
+  clear_chol_flags(st, stream);
   isvd_status rc;
   switch (op->prec) {
     case ISVD_FP64: rc = svd_same_precision<double>(op, prm, U, ldu, S, V, ldv, st, stream); break;
     case ISVD_FP32: rc = svd_same_precision<float>(op, prm, U, ldu, S, V, ldv, st, stream); break;
     default: rc = svd_bf16(op, prm, U, ldu, S, V, ldv, st, stream); break;
   }
+  read_chol_flags(st, stream);   // repairs of single passes since the last read
   if (info) {
     info->iterations = st.iterations;
     info->applies = st.applies;
@@ -585,6 +609,7 @@ void orthonormalize_block(int64_t rows, int cols, T* Y, int64_t ld, double* Rout
   st.lp = pad16(cols);
   st.ld = ld;
   st.Rc.ensure(static_cast<size_t>(st.lp) * st.lp * sizeof(double));
+  clear_chol_flags(st, stream);
   orthonormalize<T>(st, Y, rows, st.Rc.as<double>(), nullptr, stream);
   if (Rout) {
     launch_convert<double, double>(cols, cols, st.Rc.as<double>(), st.lp, Rout, cols, stream);

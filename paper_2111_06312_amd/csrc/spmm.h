@@ -47,17 +47,21 @@ struct SpmmPass {
 
 // Opt-in event timing of passes (profile.cpp).
 bool spmm_profiling();
-void* spmm_profile_begin(hipStream_t stream, double gather_bytes, double compulsory_bytes);
+void* spmm_profile_begin(hipStream_t stream, double gather_bytes, double compulsory_bytes, int elem_bytes);
 void spmm_profile_end(hipStream_t stream, void* token);
 void spmm_profile_enable(bool on);
-void spmm_profile_read(double* ms, double* gather, double* compulsory, int64_t* launches);
+// elem_bytes != 0: only the passes over blocks of that element size; clear:
+// drop the records afterwards.
+void spmm_profile_read(double* ms, double* gather, double* compulsory, int64_t* launches, int elem_bytes = 0,
+                       bool clear = true);
 
 // Timed regions of other kernels (classes 1 .. kProfileClasses - 1), recorded
 // while spmm_profiling() is on.
 constexpr int kProfileClasses = 4;
-void* profile_begin(int cls, hipStream_t stream, double bytes, double bytes2);
+void* profile_begin(int cls, hipStream_t stream, double bytes, double bytes2, int tag = 0);
 void profile_end(hipStream_t stream, void* token);
-void profile_read(int cls, double* ms, double* bytes, double* bytes2, int64_t* launches);
+void profile_read(int cls, double* ms, double* bytes, double* bytes2, int64_t* launches, int tag = 0,
+                  bool clear = true);
 
 // Launch one pass; T = storage type (double, float, bf16).
 template <typename T>

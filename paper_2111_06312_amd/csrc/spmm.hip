@@ -340,7 +340,7 @@ void launch_spmm_pass(const SpmmPass& p, hipStream_t stream) {
     double csr = 8.0 * (n + 1) + 4.0 * e + (p.values ? 4.0 * e : 0.0);
     const double gather = csr + rows + e * l * s + (p.colscale ? e * cs : 0.0);
     const double compulsory = csr + rows + n * l * s + (p.colscale ? n * cs : 0.0);
-    tok = spmm_profile_begin(stream, gather, compulsory);
+    tok = spmm_profile_begin(stream, gather, compulsory, static_cast<int>(sizeof(T)));
   }
   if (vec) launch_vec<T, C, true>(p, stream);
   else launch_vec<T, C, false>(p, stream);

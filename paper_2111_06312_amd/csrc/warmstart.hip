@@ -390,7 +390,7 @@ void ws_train_step(isvd_warmstart* ws, int64_t n, const float* F, const float* V
   launch_gram<float>(n, k, k, Z, k, Z, k, true, G, k, work, s);
   launch_gram2<float, float>(n, k, k, Z, k, V, ldv, C, k, work, s);
   // G^-1 = R^-1 R^-T  (R: Cholesky factor; R^-1 by the tall solve applied to I)
-  launch_cholesky<double>(k, G, k, 0.0, 1e-14, R64, Rc, Dc, flag, s);
+  launch_cholesky<double>(k, G, k, 0.0, 1e-14, R64, Rc, Dc, flag, 0, s);
   hipLaunchKernelGGL(identity_kernel, dim3(nb(static_cast<int64_t>(k) * lp)), dim3(256), 0, s, k, lp, Rinv);
   ISVD_LAUNCH_CHECK();
   launch_trsm_tall<double>(k, k, Rinv, lp, Rc, Dc, nullptr, nullptr, s);
@@ -498,7 +498,7 @@ void ws_omega(isvd_warmstart* ws, isvd_operator* op, const float* F, int p, uint
     work.ensure(gram_workspace_doubles(n, k, k) * sizeof(double));
     launch_gram<float>(n, k, k, Z, k, Z, k, true, G.as<double>(), k, work.as<double>(), s);
     launch_cholesky<double>(k, G.as<double>(), k, 0.0, 1e-12, R64.as<double>(), Rc.as<double>(), Dc.as<double>(),
-                            cf.as<int>(), s);
+                            cf.as<int>(), 0, s);
     int bad = 0;
     ISVD_HIP(hipMemcpyAsync(&bad, cf.p, sizeof(int), hipMemcpyDeviceToHost, s));
     ISVD_HIP(hipStreamSynchronize(s));

@@ -126,6 +126,11 @@ def load():
     lib.isvd_profile_learners_read.argtypes = [vp, vp, vp]
     lib.isvd_profile_spmm_read.argtypes = [ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
                                            ct.POINTER(ct.c_double), ct.POINTER(i64)]
+    lib.isvd_peak_copy.argtypes = [vp, vp, i64, st, ct.POINTER(ct.c_double), vp]
+    lib.isvd_peak_read.argtypes = [vp, i64, st, ct.POINTER(ct.c_double), vp]
+    lib.isvd_peak_mfma.argtypes = [st, i64, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), vp]
+    lib.isvd_profile_spmm_read_storage.argtypes = [st, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
+                                                   ct.POINTER(ct.c_double), ct.POINTER(i64)]
     _lib = lib
     return lib
 
@@ -408,6 +413,42 @@ def profile_spmm_read():
     ms, gb, cb, n = ct.c_double(), ct.c_double(), ct.c_double(), ct.c_int64()
     _check(_lib.isvd_profile_spmm_read(ct.byref(ms), ct.byref(gb), ct.byref(cb), ct.byref(n)))
     return ms.value, gb.value, cb.value, n.value
+
+
+def profile_spmm_read_storage(precision):
+    """(total_ms, gather_bytes, compulsory_bytes, launches) of the recorded
+    passes over blocks stored in `precision` (FP64, FP32 or BF16); the
+    record is kept for profile_spmm_read()."""
+    ms, gb, cb, n = ct.c_double(), ct.c_double(), ct.c_double(), ct.c_int64()
+    _check(_lib.isvd_profile_spmm_read_storage(precision, ct.byref(ms), ct.byref(gb), ct.byref(cb), ct.byref(n)))
+    return ms.value, gb.value, cb.value, n.value
+
+
+def peak_copy(src, dst, reps=1):
+    """Time `reps` device copies src -> dst (same byte size, 16-byte
+    aligned) with the library's copy kernel; returns milliseconds."""
+    load()
+    nb = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nb
+    ms = ct.c_double()
+    _check(_lib.isvd_peak_copy(_ptr(src), _ptr(dst), nb, reps, ct.byref(ms), _stream()))
+    return ms.value
+
+
+def peak_read(src, reps=1):
+    """Time one launch reading `src` `reps` times; returns milliseconds."""
+    load()
+    ms = ct.c_double()
+    _check(_lib.isvd_peak_read(_ptr(src), src.numel() * src.element_size(), reps, ct.byref(ms), _stream()))
+    return ms.value
+
+
+def peak_mfma(precision, iters):
+    """(flops, milliseconds) of back-to-back 16x16x4 MFMAs in FP64 or FP32."""
+    load()
+    fl, ms = ct.c_double(), ct.c_double()
+    _check(_lib.isvd_peak_mfma(precision, iters, ct.byref(fl), ct.byref(ms), _stream()))
+    return fl.value, ms.value
 
 
 def profile_learners_read():

@@ -41,26 +41,36 @@ def edges_to_csr(n: int, src: np.ndarray, dst: np.ndarray, blocks=None) -> Graph
     """Symmetric CSR from an undirected edge list (i != j).
 
     Duplicate pairs (in either orientation) are merged; self-pairs are
-    dropped.
+    dropped.  Row r holds its neighbours below r (pairs (lo, hi) with
+    hi = r) followed by those above r (lo = r), each run sorted, so the
+    CSR is assembled by placement after two sorts of the pair codes.
     """
     src = np.asarray(src, dtype=np.int64)
     dst = np.asarray(dst, dtype=np.int64)
     keep = src != dst
     src, dst = src[keep], dst[keep]
-    lo = np.minimum(src, dst)
-    hi = np.maximum(src, dst)
-    code = np.unique(lo * n + hi)
-    lo = code // n
-    hi = code % n
-    rows = np.concatenate([lo, hi])
-    cols = np.concatenate([hi, lo])
-    order = np.argsort(rows * n + cols, kind="stable")
-    rows = rows[order]
-    cols = cols[order]
-    counts = np.bincount(rows, minlength=n)
+    code = np.minimum(src, dst) * n + np.maximum(src, dst)
+    code.sort()
+    if code.shape[0]:
+        first = np.empty(code.shape[0], dtype=bool)
+        first[0] = True
+        np.not_equal(code[1:], code[:-1], out=first[1:])
+        code = code[first]
+    lo, hi = np.divmod(code, n)                 # sorted by (lo, hi)
+    below = hi * n + lo
+    below.sort()
+    b_row, b_col = np.divmod(below, n)          # sorted by (hi, lo)
+    cnt_b = np.bincount(b_row, minlength=n)
+    cnt_a = np.bincount(lo, minlength=n)
     indptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(counts, out=indptr[1:])
-    return Graph(n=n, indptr=indptr, indices=cols.astype(np.int32), blocks=blocks)
+    np.cumsum(cnt_b + cnt_a, out=indptr[1:])
+    start_b = np.cumsum(cnt_b) - cnt_b
+    start_a = np.cumsum(cnt_a) - cnt_a
+    rank = np.arange(code.shape[0], dtype=np.int64)
+    indices = np.empty(2 * code.shape[0], dtype=np.int32)
+    indices[indptr[b_row] + (rank - start_b[b_row])] = b_col
+    indices[indptr[lo] + cnt_b[lo] + (rank - start_a[lo])] = hi
+    return Graph(n=n, indptr=indptr, indices=indices, blocks=blocks)
 
 
 def _block_sizes(n: int, num_blocks: int) -> np.ndarray:

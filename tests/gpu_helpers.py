@@ -77,3 +77,8 @@ def sampled_triplets(k):
 # two differ by the FP32 rounding of those products, about 1e-6 relative
 # here, so a returned rho at the tolerance can read up to 1% above it.
 RHO_SLACK = 1.01
+
+
+def print_case(*a):
+    """Name the case on stdout before its GPU work (flushed)."""
+    print("CASE", *a, flush=True)

@@ -254,6 +254,18 @@ isvd_status isvd_orthonormalize_householder(int64_t rows, int64_t cols, isvd_pre
 isvd_status isvd_gram(int64_t rows, int64_t m, int64_t p, isvd_precision precision, const void* A,
                       int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc, void* stream);
 
+/* isvd_gram for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, result and error rules, but no allocation of any kind -- the
+ * row-slice partial results live in a fixed 32 MiB device array of the
+ * library (one per GPU, held until the process ends), so the number of row
+ * slices is bounded by it and sums may group differently from isvd_gram
+ * (FP64 rounding only).  Enqueued only, no synchronisation.  Every call on a
+ * GPU shares that GPU's array: calls that overlap in time on one GPU race and
+ * must be serialised by the caller (one stream, or host ordering). */
+isvd_status isvd_gram_noalloc(int64_t rows, int64_t m, int64_t p, isvd_precision precision, const void* A,
+                              int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc, void* stream);
+
 /* SVD of a small n x n FP64 matrix (n <= 1024) by one-sided Jacobi:
  * A = Uo diag(s) Vo^T, s descending.  All device, row-major, leading dim n.
  * The small Rayleigh-Ritz SVD of Algorithm 1 (its svd of B).  Enqueued only. */

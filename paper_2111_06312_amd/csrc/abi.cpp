@@ -17,6 +17,9 @@ template <typename T>
 void orthonormalize_block(int64_t rows, int cols, T* Y, int64_t ld, double* Rout, hipStream_t stream,
                           bool householder);
 
+template <typename T>
+void gram_noalloc(int64_t rows, int m, int p, const T* A, int64_t lda, const T* B, int64_t ldb, bool same, double* C,
+                  int64_t ldc, hipStream_t stream);
 double peak_copy(const void* src, void* dst, int64_t bytes, int reps, hipStream_t stream);
 double peak_read(const void* src, int64_t bytes, int reps, uint32_t* sink, hipStream_t stream);
 int64_t peak_sink_elems();
@@ -442,6 +445,34 @@ isvd_status isvd_gram(int64_t rows, int64_t m, int64_t p, isvd_precision precisi
       default: throw Error{ISVD_E_INVALID, "bad precision"};
     }
     ISVD_HIP(hipStreamSynchronize(s));  // the workspace is freed on return
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_gram_noalloc(int64_t rows, int64_t m, int64_t p, isvd_precision precision, const void* A,
+                              int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc, void* stream) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(A && B && C && rows >= 0 && m >= 1 && p >= 1 && m + p <= 2048, ISVD_E_INVALID,
+               "bad gram arguments (need m + p <= 2048)");
+    ISVD_CHECK(lda >= m && ldb >= p && ldc >= p, ISVD_E_INVALID, "leading dimension too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool same = (A == B) && (m == p) && (lda == ldb);
+    const int mi = static_cast<int>(m), pi = static_cast<int>(p);
+    switch (precision) {
+      case ISVD_FP64:
+        gram_noalloc<double>(rows, mi, pi, static_cast<const double*>(A), lda, static_cast<const double*>(B), ldb,
+                             same, C, ldc, s);
+        break;
+      case ISVD_FP32:
+        gram_noalloc<float>(rows, mi, pi, static_cast<const float*>(A), lda, static_cast<const float*>(B), ldb,
+                            same, C, ldc, s);
+        break;
+      case ISVD_BF16:
+        gram_noalloc<bf16>(rows, mi, pi, static_cast<const bf16*>(A), lda, static_cast<const bf16*>(B), ldb, same,
+                           C, ldc, s);
+        break;
+      default: throw Error{ISVD_E_INVALID, "bad precision"};
+    }
     return ISVD_OK;
   });
 }

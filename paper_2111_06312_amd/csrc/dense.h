@@ -17,6 +17,13 @@ template <typename T>
 void launch_gram(int64_t rows, int m, int p, const T* A, int64_t lda, const T* B, int64_t ldb,
                  bool same, double* C, int64_t ldc, double* work, hipStream_t stream);
 
+// launch_gram with a workspace of `work_doubles` doubles: as many row slices
+// as the workspace holds (at most the default count); throws ISVD_E_INVALID
+// when it cannot hold one slice's m x p partial result.
+template <typename T>
+void launch_gram_bounded(int64_t rows, int m, int p, const T* A, int64_t lda, const T* B, int64_t ldb, bool same,
+                         double* C, int64_t ldc, double* work, size_t work_doubles, hipStream_t stream);
+
 // Feature-side variant: A of type TA (features), B of type TB.
 template <typename TA, typename TB>
 void launch_gram2(int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,

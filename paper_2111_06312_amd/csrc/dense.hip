@@ -385,15 +385,15 @@ struct GramPlan {
 
 // Row slices: at most kGramMaxParts (one per CU), each a multiple of 16 rows
 // (at least 64), so that large blocks use every CU.
-int64_t gram_rows_per_part(int64_t rows) {
-  const int64_t want = ceil_div(rows > 0 ? rows : 1, kGramMaxParts);
+int64_t gram_rows_per_part(int64_t rows, int max_parts = kGramMaxParts) {
+  const int64_t want = ceil_div(rows > 0 ? rows : 1, max_parts);
   return round_up(want < 64 ? 64 : want, 16);
 }
 
 constexpr int kGramCS2[] = {1, 2, 3, 4, 5, 6, 8, 16};   // paired-column loads
 constexpr int kGramCS1[] = {1, 2, 4, 8, 16, 32};          // one column per load
 
-GramPlan plan_gram(int64_t rows, int m, int p, bool same, int esize, bool paired) {
+GramPlan plan_gram(int64_t rows, int m, int p, bool same, int esize, bool paired, int max_parts) {
   GramPlan g;
   g.mp = pad16(m);
   g.pp = pad16(p);
@@ -447,7 +447,7 @@ GramPlan plan_gram(int64_t rows, int m, int p, bool same, int esize, bool paired
   // the second wave of each shared job hands its accumulators over in LDS
   if (g.ksplit == 2)
     g.lds = std::max(g.lds, static_cast<size_t>(g.waves / 2) * kGramRB * kGramRB * 4 * 64 * sizeof(double));
-  g.rows_per_block = gram_rows_per_part(rows);
+  g.rows_per_block = gram_rows_per_part(rows, max_parts);
   g.nparts = static_cast<int>(ceil_div(rows > 0 ? rows : 1, g.rows_per_block));
   return g;
 }
@@ -488,12 +488,12 @@ bool gram_pair_ok(const T* ptr, int64_t ld) {
 
 template <typename TA, typename TB>
 void gram_impl(int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
-               bool same, double* C, int64_t ldc, double* work, hipStream_t stream) {
+               bool same, double* C, int64_t ldc, double* work, hipStream_t stream, int max_parts = kGramMaxParts) {
   using S = typename GramStage<TA, TB>::type;
   // BF16 pairs are loaded as one word without a tail case: even column counts only
   const bool even_cols = (!std::is_same<TA, bf16>::value || m % 2 == 0) && (!std::is_same<TB, bf16>::value || p % 2 == 0);
   const bool paired = gram_pair_ok(A, lda) && (same || gram_pair_ok(B, ldb)) && even_cols;
-  const GramPlan g = plan_gram(rows, m, p, same, static_cast<int>(sizeof(S)), paired);
+  const GramPlan g = plan_gram(rows, m, p, same, static_cast<int>(sizeof(S)), paired, max_parts);
   if (paired) {
     switch (g.cs) {
       case 1: gram_launch_cs<TA, TB, 1, 2>(g, rows, m, p, A, lda, B, ldb, same, work, stream); break;
@@ -1952,6 +1952,23 @@ void launch_gram(int64_t rows, int m, int p, const T* A, int64_t lda, const T* B
                  double* C, int64_t ldc, double* work, hipStream_t stream) {
   gram_impl<T, T>(rows, m, p, A, lda, B, ldb, same, C, ldc, work, stream);
 }
+
+int gram_max_parts_for(int m, int p, size_t work_doubles) {
+  const size_t per_part = static_cast<size_t>(pad16(m)) * pad16(p);
+  const size_t parts = per_part ? work_doubles / per_part : 0;
+  return static_cast<int>(parts < static_cast<size_t>(kGramMaxParts) ? parts : kGramMaxParts);
+}
+
+template <typename T>
+void launch_gram_bounded(int64_t rows, int m, int p, const T* A, int64_t lda, const T* B, int64_t ldb, bool same,
+                         double* C, int64_t ldc, double* work, size_t work_doubles, hipStream_t stream) {
+  const int parts = gram_max_parts_for(m, p, work_doubles);
+  ISVD_CHECK(parts >= 1, ISVD_E_INVALID, "gram: the workspace cannot hold one row slice of the result");
+  gram_impl<T, T>(rows, m, p, A, lda, B, ldb, same, C, ldc, work, stream, parts);
+}
+template void launch_gram_bounded<double>(int64_t, int, int, const double*, int64_t, const double*, int64_t, bool, double*, int64_t, double*, size_t, hipStream_t);
+template void launch_gram_bounded<float>(int64_t, int, int, const float*, int64_t, const float*, int64_t, bool, double*, int64_t, double*, size_t, hipStream_t);
+template void launch_gram_bounded<bf16>(int64_t, int, int, const bf16*, int64_t, const bf16*, int64_t, bool, double*, int64_t, double*, size_t, hipStream_t);
 template <typename TA, typename TB>
 void launch_gram2(int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb,
                   double* C, int64_t ldc, double* work, hipStream_t stream) {

@@ -106,6 +106,7 @@ def load():
     lib.isvd_orthonormalize.argtypes = [i64, i64, st, vp, i64, vp, vp]
     lib.isvd_orthonormalize_householder.argtypes = [i64, i64, st, vp, i64, vp, vp]
     lib.isvd_gram.argtypes = [i64, i64, i64, st, vp, i64, vp, i64, vp, i64, vp]
+    lib.isvd_gram_noalloc.argtypes = [i64, i64, i64, st, vp, i64, vp, i64, vp, i64, vp]
     lib.isvd_small_svd.argtypes = [i64, vp, vp, vp, vp, vp]
     lib.isvd_ws_features.argtypes = [vp, vp, vp]
     lib.isvd_ws_create.argtypes = [st, ct.c_uint64, ct.POINTER(vp)]
@@ -494,6 +495,17 @@ def gram(A, B=None):
     C = torch.empty((A.shape[1], B.shape[1]), dtype=torch.float64, device=A.device)
     _check(_lib.isvd_gram(A.shape[0], A.shape[1], B.shape[1], _PREC[A.dtype], _ptr(A), _ld(A), _ptr(B), _ld(B),
                           _ptr(C), C.shape[1], _stream()))
+    return C
+
+
+def gram_noalloc(A, B, C):
+    """C <- A^T B in FP64 through isvd_gram_noalloc (no allocation by the
+    library; C is the caller's m x p FP64 tensor); enqueued on the current
+    stream."""
+    load()
+    assert C.dtype == torch.float64 and C.shape == (A.shape[1], B.shape[1])
+    _check(_lib.isvd_gram_noalloc(A.shape[0], A.shape[1], B.shape[1], _PREC[A.dtype], _ptr(A), _ld(A), _ptr(B),
+                                  _ld(B), _ptr(C), _ld(C), _stream()))
     return C
 
 

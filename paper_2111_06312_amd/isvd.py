@@ -9,6 +9,7 @@ built (paper_2111_06312_amd/build.py); there is no fallback path.
 from __future__ import annotations
 
 import ctypes as ct
+import numbers
 import os
 from dataclasses import dataclass
 
@@ -348,6 +349,15 @@ class Dag:
         ids = self._ids(nodes)
         return self._node(_lib.isvd_dag_product, len(nodes), ids)
 
+    def power(self, node, p):
+        """node^p as a product of p references to node (p a positive integer)."""
+        if isinstance(p, bool) or not isinstance(p, numbers.Integral) or p < 1:
+            raise ValueError(f"matrix powers are positive integers, got {p!r}")
+        factors = []
+        for _ in range(int(p)):
+            factors.append(node)
+        return self.product(factors)
+
     def concat_cols(self, nodes):
         ids = self._ids(nodes)
         return self._node(_lib.isvd_dag_concat_cols, len(nodes), ids)
@@ -377,23 +387,6 @@ class DagNode:
         _check(_lib.isvd_dag_shape(dag.handle, nid, ct.byref(r), ct.byref(c)))
         self.shape = (r.value, c.value)
 
-    def __add__(self, other):
-        return self.dag.sum([self, other])
-
-    def __sub__(self, other):
-        return self.dag.sum([self, other], [1.0, -1.0])
-
-    def __mul__(self, alpha):
-        return self.dag.sum([self], [float(alpha)])
-
-    __rmul__ = __mul__
-
-    def __matmul__(self, other):
-        return self.dag.product([self, other])
-
-    def __pow__(self, p):
-        return self.dag.product([self] * int(p))
-
     @property
     def T(self):
         return self.dag._node(_lib.isvd_dag_transpose, self.id)
@@ -401,6 +394,29 @@ class DagNode:
     def gather_rows(self, rows):
         r = torch.as_tensor(rows, dtype=torch.int64, device=self.dag.device).contiguous()
         return self.dag._node(_lib.isvd_dag_gather_rows, self.id, _ptr(r), r.shape[0])
+
+
+
+def _same_dag_node(fn):
+    def op(a, b):
+        return fn(a, b) if isinstance(b, DagNode) else NotImplemented
+    return op
+
+
+def _scaled_node(a, s):
+    return a.dag.sum([a], [float(s)]) if isinstance(s, numbers.Real) else NotImplemented
+
+
+# a + b, a - b, s * a, a @ b and a ** p build DAG nodes (one C call each)
+for _name, _fn in {
+    "__add__": _same_dag_node(lambda a, b: a.dag.sum([a, b])),
+    "__sub__": _same_dag_node(lambda a, b: a.dag.sum([a, b], [1.0, -1.0])),
+    "__matmul__": _same_dag_node(lambda a, b: a.dag.product([a, b])),
+    "__mul__": _scaled_node,
+    "__rmul__": _scaled_node,
+    "__pow__": lambda a, p: a.dag.power(a, p),
+}.items():
+    setattr(DagNode, _name, _fn)
 
 
 def profile_spmm(on=True):

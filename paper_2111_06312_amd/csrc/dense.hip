@@ -1191,11 +1191,12 @@ __global__ void upper_mult_kernel(int lp, const double* A, const double* B, doub
 // registers, and lane (li, lk) reads and writes elements drow(lk, 0..3) of
 // row li of its 16-row tile (four consecutive FP32 values).
 //
-// The A operands R_JK^T and D_K^T are packed once per factor: tiles (J, K),
+// The A operands -R_JK^T and D_K^T are packed once per factor: tiles (J, K),
 // J <= K, column tile by column tile (tile index K (K + 1) / 2 + J), 256
-// entries each, entry (16 lk + li) 4 + kk holding R[16 J + drow(lk, kk)][16 K + li]
-// (J < K) or D_K[drow(lk, kk)][li] (J = K): one 16-byte read per lane gives the
-// four k-steps.
+// entries each, entry (16 lk + li) 4 + kk holding -R[16 J + drow(lk, kk)][16 K + li]
+// (J < K, negated so that the MFMAs subtract with no extra instruction) or
+// D_K[drow(lk, kk)][li] (J = K): one 16-byte read per lane gives the four
+// k-steps.
 template <typename C>
 __global__ void rfrag_pack_kernel(int lp, const double* R, const double* Dinv, C* Rf) {
   const int TT = lp / 16;
@@ -1207,7 +1208,7 @@ __global__ void rfrag_pack_kernel(int lp, const double* R, const double* Dinv, C
   const int J = t - K * (K + 1) / 2;
   const int kk = e & 3, li = (e >> 2) & 15, lk = e >> 6;
   const int a = drow<C>(lk, kk);
-  const double v = (J < K) ? R[static_cast<int64_t>(16 * J + a) * lp + 16 * K + li] : Dinv[K * 256 + a * 16 + li];
+  const double v = (J < K) ? -R[static_cast<int64_t>(16 * J + a) * lp + 16 * K + li] : Dinv[K * 256 + a * 16 + li];
   Rf[idx] = static_cast<C>(v);
 }
 
@@ -1382,7 +1383,7 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* 
           C a[4];
           load_frag4<C>(rk + 256 * J, a);
   #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) acc[J & 3] = mfma4(-a[kk], q[J][kk], acc[J & 3]);
+          for (int kk = 0; kk < 4; ++kk) acc[J & 3] = mfma4(a[kk], q[J][kk], acc[J & 3]);
         }
         const V sacc = (acc[0] + acc[1]) + (acc[2] + acc[3]);
         C d[4];
@@ -1457,7 +1458,7 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* 
           for (int g = 0; g < kGroup; ++g) {
             if (J0 + g >= MT || J0 + g >= K) continue;
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) acc[g & 3] = mfma4(-a[g][kk], q[J0 + g][kk], acc[g & 3]);
+            for (int kk = 0; kk < 4; ++kk) acc[g & 3] = mfma4(a[g][kk], q[J0 + g][kk], acc[g & 3]);
           }
         }
         const V sacc = (acc[0] + acc[1]) + (acc[2] + acc[3]);
@@ -1520,6 +1521,166 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* 
     __syncthreads();
     for (int col = threadIdx.x; col < l; col += blockDim.x)
       colpart[static_cast<int64_t>(blockIdx.x) * l + col] = (csw[0][col] + csw[1][col]) + (csw[2][col] + csw[3][col]);
+  }
+}
+
+// Wide FP32 solve for blocks of exactly 16 MT columns (MT = 16 or 18), rows
+// 16-byte aligned: the off-diagonal tiles of the packed factor (MT (MT - 1) / 2
+// KiB; 153 KiB at l = 288) are copied once into the LDS of a persistent
+// workgroup of W waves, one workgroup per CU; the diagonal inverses come from
+// global memory (L2), one tile ahead of use.  A wave walks 16-row tiles as
+// trsm_rows_kernel does.  Y is read through a ring of MT / 2 tile slots:
+// consuming tile K of the current row tile frees slot K mod MT / 2, which
+// receives tile K + MT / 2 of the same row tile or, in the second half, tile
+// K - MT / 2 of the wave's next row tile.  Every access is a whole 16-byte
+// (FP32) or 8-byte (BF16) word; only stores of rows past the end are masked.
+// Column sums: after each column tile the 16 rows' values are summed in FP64
+// across the lanes of a column (shuffles) and lane li keeps the sums of the
+// tiles K with K mod 16 == li.
+template <typename T> __device__ inline void load_full_tile(const T* rowp, int K, int lk, float (&v)[4]);
+template <> __device__ inline void load_full_tile<float>(const float* rowp, int K, int lk, float (&v)[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(rowp + 16 * K + 4 * lk);
+  v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+}
+template <> __device__ inline void load_full_tile<bf16>(const bf16* rowp, int K, int lk, float (&v)[4]) {
+  const uint2 q = *reinterpret_cast<const uint2*>(rowp + 16 * K + 4 * lk);
+  v[0] = __uint_as_float(q.x);   // two packed words, widened by widen_tile_row
+  v[1] = __uint_as_float(q.y);
+  v[2] = v[3] = 0.f;
+}
+
+template <typename T, int MT, int W>
+__global__ __launch_bounds__(64 * W) void trsm_wide_kernel(int64_t rows, T* Y, int64_t ld, const float* Rf,
+                                                           double* colpart) {
+  using C = float;
+  using V = v4f;
+  constexpr int NS = (MT + 15) / 16;
+  constexpr int H = MT / 2;   // ring slots
+  constexpr int L = 16 * MT;
+  extern __shared__ __align__(16) unsigned char trsm_smem[];
+  float* off = reinterpret_cast<float*>(trsm_smem);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  {
+    // LDS tile K (K - 1) / 2 + J  <-  packed tile K (K + 1) / 2 + J, J < K
+    constexpr int n16 = MT * (MT - 1) / 2 * 64;
+    for (int f = threadIdx.x; f < n16; f += blockDim.x) {
+      const int t = f >> 6, e = f & 63;
+      int K = 1;
+      while (K * (K + 1) / 2 <= t) ++K;
+      const int J = t - K * (K - 1) / 2;
+      reinterpret_cast<float4*>(off)[f] =
+          reinterpret_cast<const float4*>(Rf + static_cast<int64_t>(K * (K + 1) / 2 + J) * 256)[e];
+    }
+    __syncthreads();
+  }
+  double cacc[NS][4];
+#pragma unroll
+  for (int s2 = 0; s2 < NS; ++s2)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cacc[s2][r] = 0.0;
+  const int64_t ntiles = (rows + 15) / 16;
+  const int64_t tstride = static_cast<int64_t>(gridDim.x) * W;
+  int64_t rt = static_cast<int64_t>(blockIdx.x) * W + wave;
+  auto clamp_row = [&](int64_t tile) {
+    const int64_t r = tile * 16 + li;
+    return Y + (r < rows ? r : rows - 1) * ld;
+  };
+  C yb[H][4];
+  {
+    const T* rowp = clamp_row(rt < ntiles ? rt : 0);
+#pragma unroll
+    for (int K = 0; K < H; ++K) load_full_tile<T>(rowp, K, lk, yb[K]);
+  }
+  for (; rt < ntiles; rt += tstride) {
+    const int64_t row0 = rt * 16;
+    const bool rok = row0 + li < rows;
+    T* rowp = Y + (row0 + li) * ld;
+    const T* crowp = clamp_row(rt);
+    const T* nrowp = clamp_row(rt + tstride < ntiles ? rt + tstride : rt);
+    C q[MT][4];
+    C dn[4];
+    load_frag4<C>(Rf + 4 * lane, dn);   // D_0 (packed tile 0)
+#pragma unroll
+    for (int K = 0; K < MT; ++K) {
+      C d[4] = {dn[0], dn[1], dn[2], dn[3]};
+      if (K + 1 < MT) load_frag4<C>(Rf + static_cast<int64_t>((K + 1) * (K + 4) / 2) * 256 + 4 * lane, dn);
+      C y[4] = {yb[K % H][0], yb[K % H][1], yb[K % H][2], yb[K % H][3]};
+      widen_tile_row<T, C>(y);
+      if (K + H < MT) load_full_tile<T>(crowp, K + H, lk, yb[K % H]);
+      else load_full_tile<T>(nrowp, K + H - MT, lk, yb[K % H]);
+      V acc[4];
+      acc[0] = V{y[0], y[1], y[2], y[3]};
+      acc[1] = acc[2] = acc[3] = V{0, 0, 0, 0};
+      const float* rk = off + (K * (K - 1) / 2) * 256 + 4 * lane;
+      // tiles J of a group of four feed the four accumulators in turn, so
+      // consecutive MFMAs never depend on each other; the next group's factor
+      // fragments are read from LDS while the current group's MFMAs run (one
+      // group ahead only: the scheduling barrier keeps the registers bounded)
+      C a[4][4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        if (g < K) load_frag4<C>(rk + 256 * g, a[g]);
+#pragma unroll
+      for (int J0 = 0; J0 < K; J0 += 4) {
+        C an[4][4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          if (J0 + 4 + g < K) load_frag4<C>(rk + 256 * (J0 + 4 + g), an[g]);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+          for (int g = 0; g < 4; ++g)
+            if (J0 + g < K) acc[g] = mfma4(a[g][kk], q[J0 + g][kk], acc[g]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) a[g][kk] = an[g][kk];
+      }
+      const V sacc = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+      // D_K^T applied with two accumulators (k-steps 0, 1 and 2, 3)
+      V out = V{0, 0, 0, 0}, out2 = V{0, 0, 0, 0};
+      out = mfma4(d[0], sacc[0], out);
+      out2 = mfma4(d[2], sacc[2], out2);
+      out = mfma4(d[1], sacc[1], out);
+      out2 = mfma4(d[3], sacc[3], out2);
+      out += out2;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) q[K][r] = out[r];
+      store_tile_row<T, C>(rowp, K, lk, L, rok, true, q[K]);
+      if (colpart) {
+        double cs[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          cs[r] = rok ? static_cast<double>(stored_as<T, C>(q[K][r])) : 0.0;
+#pragma unroll
+          for (int m = 1; m < 16; m <<= 1) cs[r] += __shfl_xor(cs[r], m, 64);
+        }
+        if (li == (K & 15)) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) cacc[K >> 4][r] += cs[r];
+        }
+      }
+    }
+  }
+  if (colpart) {
+    __syncthreads();   // every wave is done with the factor: its LDS takes the sums
+    double* csw = reinterpret_cast<double*>(trsm_smem);
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) {
+      const int K = li + 16 * s2;
+      if (K < MT) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) csw[wave * L + 16 * K + drow<C>(lk, r)] = cacc[s2][r];
+      }
+    }
+    __syncthreads();
+    for (int col = threadIdx.x; col < L; col += blockDim.x) {
+      double v = 0.0;
+      for (int w = 0; w < W; ++w) v += csw[w * L + col];
+      colpart[static_cast<int64_t>(blockIdx.x) * L + col] = v;
+    }
   }
 }
 
@@ -2077,6 +2238,22 @@ template void launch_trsm_rows_pack<double>(int, const double*, const double*, d
 template void launch_trsm_rows_pack<float>(int, const double*, const double*, float*, hipStream_t);
 
 constexpr size_t kTrsmRowsMaxLds = 96 * 1024;
+constexpr int kTrsmWideWaves = 8;
+
+// LDS bytes a workgroup may use on the current device (cached per device).
+size_t lds_per_block() {
+  static std::mutex mu;
+  static std::map<int, size_t> cache;
+  int dev = 0;
+  ISVD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int v = 0;
+  ISVD_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  cache.emplace(dev, static_cast<size_t>(v > 0 ? v : 0));
+  return static_cast<size_t>(v > 0 ? v : 0);
+}
 
 // Workgroups of `fn` (threads, dynamic LDS bytes) the current device holds at
 // once; cached per (kernel, LDS, device).
@@ -2117,6 +2294,22 @@ int64_t trsm_rows_launch(int64_t rows, int l, T* Y, int64_t ld, int vec, const C
       hipLaunchKernelGGL((trsm_rows_kernel<T, C, MT, false>), dim3(static_cast<unsigned>(grid)), dim3(256), 0,
                          stream, rows, l, Y, ld, vec, Rf, colpart);
   } else {
+    if constexpr (std::is_same<C, float>::value && (MT == 16 || MT == 18)) {
+      // whole tiles, aligned rows: the off-diagonal tiles in the LDS of one workgroup per CU
+      const size_t lds = static_cast<size_t>(MT) * (MT - 1) / 2 * 256 * sizeof(float);
+      const size_t sums = static_cast<size_t>(kTrsmWideWaves) * 16 * MT * sizeof(double);
+      const size_t need = lds > sums ? lds : sums;
+      if (l == 16 * MT && vec && need <= lds_per_block()) {
+        const void* fn = reinterpret_cast<const void*>(&trsm_wide_kernel<T, MT, kTrsmWideWaves>);
+        const int64_t resident = resident_workgroups(fn, 64 * kTrsmWideWaves, need);
+        const int64_t want = ceil_div(ceil_div(rows, 16), kTrsmWideWaves);
+        grid = std::min<int64_t>(std::min<int64_t>(resident, want), kRowsTrsmParts);
+        hipLaunchKernelGGL((trsm_wide_kernel<T, MT, kTrsmWideWaves>), dim3(static_cast<unsigned>(grid)),
+                           dim3(64 * kTrsmWideWaves), need, stream, rows, Y, ld, Rf, colpart);
+        ISVD_LAUNCH_CHECK();
+        return grid;
+      }
+    }
     // the factor is read from global memory (it does not fit in LDS)
     const int64_t resident =
         resident_workgroups(reinterpret_cast<const void*>(&trsm_rows_kernel<T, C, MT, false>), 256, 0);

@@ -12,7 +12,7 @@ import torch
 from gpu_helpers import col_rel_err, gapped_k, rounded, to_dev, to_np
 from oracle.isvd import isvd as oracle_isvd, principal_angles
 from oracle.operators import FeatPropDesignMatrix, NEDesignMatrix
-from oracle import symbolic as S
+from oracle import symbolic as sym
 from synth import CONFIGS, block_features, chung_lu_graph, gaussian_block, sbm_graph
 from synth.configs import make_graph
 
@@ -124,7 +124,7 @@ def test_every_node_type_against_the_oracle(gpu_lib, precision):
                    t_indices=ct_.indices, t_values=ct_.data)
     B = dag.dense(to_dev(b, dt))
     D = dag.diag(d)
-    oA, oC, oB, oD = S.sparse(a), S.sparse(c), S.dense(b), S.diag(d)
+    oA, oC, oB, oD = sym.sparse(a), sym.sparse(c), sym.dense(b), sym.diag(d)
     rows = rng.choice(700, 250, replace=False)
     cols = np.random.default_rng(70).choice(500, 120, replace=False)
     cases = [
@@ -133,12 +133,12 @@ def test_every_node_type_against_the_oracle(gpu_lib, precision):
         (D @ C @ D, oD @ oC @ oD),
         (C ** 3 - 0.5 * D, oC ** 3 - 0.5 * oD),
         ((A @ B).T @ (C @ A @ B), (oA @ oB).T @ (oC @ oA @ oB)),
-        ((C @ A).gather_rows(rows), S.take_rows(oC @ oA, rows)),
-        ((C @ A).gather_rows(rows).T, S.take_rows(oC @ oA, rows).T),
-        (dag.concat_cols([A, C, D @ A]), S.hstack([oA, oC, oD @ oA])),
-        (dag.concat_cols([A, C]).T, S.hstack([oA, oC]).T),
+        ((C @ A).gather_rows(rows), sym.take_rows(oC @ oA, rows)),
+        ((C @ A).gather_rows(rows).T, sym.take_rows(oC @ oA, rows).T),
+        (dag.concat_cols([A, C, D @ A]), sym.hstack([oA, oC, oD @ oA])),
+        (dag.concat_cols([A, C]).T, sym.hstack([oA, oC]).T),
         # a column gather M[:, cols] is the transpose of a row gather of M^T
-        ((C @ A).T.gather_rows(cols).T, S.take_rows((oC @ oA).T, cols).T),
+        ((C @ A).T.gather_rows(cols).T, sym.take_rows((oC @ oA).T, cols).T),
         (2.0 * (C @ C + D) @ C - C, 2.0 * (oC @ oC + oD) @ oC - oC),
     ]
     for i, (node, ref) in enumerate(cases):

@@ -127,3 +127,33 @@ def test_invalid_requests(gpu_lib):
     with pytest.raises(gpu_lib.IsvdError):
         gop.truncated_svd(0, 4, q=1)
     gop.close()
+
+
+@pytest.mark.parametrize("k,p,n", [(256, 32, 5003), (224, 32, 4000), (240, 32, 3001)])
+def test_wide_blocks_fp32_against_oracle(gpu_lib, k, p, n):
+    """Blocks of 288 and 256 columns take the LDS-resident wide triangular
+    solve (with the FP64 column sums 1^T Q of the NE products); 272 columns
+    take the general one.  Row counts leave a ragged last tile."""
+    cfg = CONFIGS["c4"].scaled(n)
+    _case("wide", cfg.name, n, k + p)
+    g = make_graph(cfg)
+    gop, oop = ne_pair(gpu_lib, g, cfg.coeffs, cfg.lam, cfg.self_loops, 1)
+    _compare(gop, oop, k, p, 2, 1, 1e-4, 1e-3, cfg.omega_seed)
+    gop.close()
+
+
+@pytest.mark.parametrize("l", [288, 256])
+def test_wide_orthonormalize_fp32_bf16(gpu_lib, l):
+    """CholeskyQR2 through the wide solve against LAPACK's R (|diag|) and
+    orthonormality, FP32 and BF16 storage, 20,007 rows (ragged)."""
+    _case("wide orth", l)
+    rows = 20007
+    y = gaussian_block(rows, l, seed=9) @ np.diag(np.logspace(0, 3, l))
+    _, rl = np.linalg.qr(y)
+    for dt, tol in ((torch.float32, 1e-6), (torch.bfloat16, 2e-3)):
+        yr = rounded(y, dt)
+        q, r = gpu_lib.orthonormalize(to_dev(yr, dt))
+        qn = to_np(q).astype(np.float64)
+        assert np.abs(qn.T @ qn - np.eye(l)).max() < 10 * tol
+        assert np.abs(qn @ to_np(r) - yr).max() <= 10 * tol * np.abs(yr).max()
+        assert np.allclose(np.abs(np.diag(to_np(r))), np.abs(np.diag(rl)), rtol=1e3 * tol)

@@ -8,7 +8,7 @@ import scipy.sparse as sp
 import torch
 
 from gpu_helpers import col_rel_err, gapped_k, rounded, to_dev, to_np
-from oracle import symbolic as S
+from oracle import symbolic as sym
 from synth import block_features, gaussian_block, sbm_graph
 
 pytestmark = pytest.mark.gpu
@@ -30,8 +30,8 @@ def _leaves(lib, g, precision):
     R = dag.diag(1.0 / np.sqrt(d1))
     Dinv1 = dag.diag(1.0 / d1)
     ah = R @ AI @ R
-    oah = S.diag(1.0 / np.sqrt(d1)) @ S.sparse(ai) @ S.diag(1.0 / np.sqrt(d1))
-    return dag, dict(A=A, ah=ah, Dinv1=Dinv1), dict(A=S.sparse(a), ah=oah, Dinv1=S.diag(1.0 / d1))
+    oah = sym.diag(1.0 / np.sqrt(d1)) @ sym.sparse(ai) @ sym.diag(1.0 / np.sqrt(d1))
+    return dag, dict(A=A, ah=ah, Dinv1=Dinv1), dict(A=sym.sparse(a), ah=oah, Dinv1=sym.diag(1.0 / d1))
 
 
 def _products(op, ref, dt, tol, l=10, seed=5):
@@ -48,8 +48,8 @@ def test_symmetric_ne_form_gives_equal_left_and_right_embeddings(gpu_lib):
     one = dag.dense(torch.ones((g.n, 1), dtype=torch.float64, device="cuda"))
     c = [0.5, 0.3, 0.2]
     m = dag.sum([d["ah"] ** j for j in (1, 2, 3)], c) - 0.05 * (one @ one.T - d["A"])
-    om = S.dense(np.ones((g.n, 1)))
-    ref = S.lincomb([o["ah"] ** j for j in (1, 2, 3)], c) - 0.05 * (om @ om.T - o["A"])
+    om = sym.dense(np.ones((g.n, 1)))
+    ref = sym.lincomb([o["ah"] ** j for j in (1, 2, 3)], c) - 0.05 * (om @ om.T - o["A"])
     op = dag.operator(m)
     _products(op, ref, torch.float64, 1e-12)
     U, S, V, info = op.truncated_svd(24, 16, tol=1e-8, max_iter=2000, seed=3)
@@ -76,8 +76,8 @@ def test_label_reuse_design_matrix(gpu_lib, precision, tol):
     b = d["ah"] - d["Dinv1"]
     m = dag.concat_cols([X, d["ah"] @ X, d["ah"] @ d["ah"] @ X, b @ Y, b @ b @ Y])
     ob = o["ah"] - o["Dinv1"]
-    oX, oY = S.dense(x), S.dense(ytr)
-    ref = S.hstack([oX, o["ah"] @ oX, o["ah"] @ o["ah"] @ oX, ob @ oY, ob @ ob @ oY])
+    oX, oY = sym.dense(x), sym.dense(ytr)
+    ref = sym.hstack([oX, o["ah"] @ oX, o["ah"] @ o["ah"] @ oX, ob @ oY, ob @ ob @ oY])
     op = dag.operator(m)
     assert op.shape == ref.shape == (g.n, 8 * 3 + 12)
     _products(op, ref, dt, tol)
@@ -97,9 +97,9 @@ def test_pseudo_dropout_row_stacking(gpu_lib):
     m = dag.concat_cols([X, d["ah"] @ X, d["ah"] ** 2 @ X])
     mpd = dag.concat_cols([XPD, d["ah"] @ XPD, d["ah"] ** 2 @ XPD])
     stacked = dag.concat_cols([m.T, mpd.T]).T
-    oX, oXPD = S.dense(x), S.dense(xpd)
-    ref = S.vstack([S.hstack([oX, o["ah"] @ oX, o["ah"] ** 2 @ oX]),
-                        S.hstack([oXPD, o["ah"] @ oXPD, o["ah"] ** 2 @ oXPD])])
+    oX, oXPD = sym.dense(x), sym.dense(xpd)
+    ref = sym.vstack([sym.hstack([oX, o["ah"] @ oX, o["ah"] ** 2 @ oX]),
+                        sym.hstack([oXPD, o["ah"] @ oXPD, o["ah"] ** 2 @ oXPD])])
     op = dag.operator(stacked)
     assert op.shape == ref.shape == (2 * g.n, 30)
     _products(op, ref, torch.float64, 1e-12)

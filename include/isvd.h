@@ -469,9 +469,11 @@ isvd_status isvd_ws_train_step(isvd_warmstart* ws, int64_t n, const float* F, co
                                void* stream);
 
 /* Start block for isvd_truncated_svd from the network: omega (n x (k+p),
- * ld ld_omega, operator precision) = [MLP(F), Gaussian(seed) p columns].
- * Falls back to an all-Gaussian block (and sets *used_fallback = 1) when the
- * network output is not finite or not of full column rank.  Synchronises. */
+ * ld ld_omega, operator precision) = [sqrt(n) Q, Gaussian(seed) p columns]
+ * with Q R = MLP(F) one Cholesky QR pass (orthonormal columns of the norm of
+ * the Gaussian ones).  Falls back to an all-Gaussian block (and sets
+ * *used_fallback = 1) when the network output is not finite or not of full
+ * column rank.  Synchronises. */
 isvd_status isvd_ws_omega(isvd_warmstart* ws, isvd_operator* op, const float* F, int p,
                           uint64_t seed, void* omega, int64_t ld_omega, int* used_fallback,
                           void* stream);

@@ -269,12 +269,12 @@ __global__ void finite_kernel(int64_t total, const float* z, int* flag) {
 }
 
 template <typename T>
-__global__ void omega_pack_kernel(int64_t n, int k, const float* Z, T* omega, int64_t ld) {
+__global__ void omega_pack_kernel(int64_t n, int k, const float* Z, float scale, T* omega, int64_t ld) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n * k) return;
   const int64_t r = i / k;
   const int c = static_cast<int>(i % k);
-  Elem<T>::store(omega + r * ld + c, static_cast<typename ComputeOf<T>::type>(Z[i]));
+  Elem<T>::store(omega + r * ld + c, static_cast<typename ComputeOf<T>::type>(scale * Z[i]));
 }
 
 unsigned nb(int64_t total) { return static_cast<unsigned>(ceil_div(total > 0 ? total : 1, 256)); }
@@ -487,41 +487,47 @@ void ws_omega(isvd_warmstart* ws, isvd_operator* op, const float* F, int p, uint
   ISVD_HIP(hipStreamSynchronize(s));
   bool ok = finite != 0;
   if (ok) {
-    // full column rank: Cholesky of Z^T Z must succeed
+    // full column rank: Cholesky of Z^T Z must succeed; then one Cholesky QR
+    // pass, Z <- Z R^-1, hands Algorithm 1 orthonormal columns instead of the
+    // raw (possibly ill-conditioned) network output
     const int lp = pad16(k);
     DevBuf G, R64, Rc, Dc, cf, work;
     G.ensure(static_cast<size_t>(k) * k * sizeof(double));
     R64.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
-    Rc.ensure(static_cast<size_t>(lp) * lp * sizeof(double));
-    Dc.ensure(static_cast<size_t>(lp) * 16 * sizeof(double));
+    Rc.ensure(static_cast<size_t>(lp) * lp * sizeof(float));
+    Dc.ensure(static_cast<size_t>(lp) * 16 * sizeof(float));
     cf.ensure(sizeof(int));
     work.ensure(gram_workspace_doubles(n, k, k) * sizeof(double));
     launch_gram<float>(n, k, k, Z, k, Z, k, true, G.as<double>(), k, work.as<double>(), s);
-    launch_cholesky<double>(k, G.as<double>(), k, 0.0, 1e-12, R64.as<double>(), Rc.as<double>(), Dc.as<double>(),
-                            cf.as<int>(), 0, s);
+    launch_cholesky<float>(k, G.as<double>(), k, 0.0, 1e-12, R64.as<double>(), Rc.as<float>(), Dc.as<float>(),
+                           cf.as<int>(), 0, s);
     int bad = 0;
     ISVD_HIP(hipMemcpyAsync(&bad, cf.p, sizeof(int), hipMemcpyDeviceToHost, s));
     ISVD_HIP(hipStreamSynchronize(s));
     ok = bad == 0;
+    if (ok) launch_trsm_tall<float>(n, k, Z, k, Rc.as<float>(), Dc.as<float>(), nullptr, nullptr, s);
+    ISVD_HIP(hipStreamSynchronize(s));   // the factors are freed on leaving this block
   }
+  // orthonormal columns scaled to the norm of the Gaussian columns beside them
+  const float zscale = std::sqrt(static_cast<float>(n));
   const int l = k + p;
   switch (op->prec) {
     case ISVD_FP64: {
       double* o = static_cast<double*>(omega);
       launch_gaussian<double>(n, l, seed, o, ld, s);
-      if (ok) hipLaunchKernelGGL(omega_pack_kernel<double>, dim3(nb(n * k)), dim3(256), 0, s, n, k, Z, o, ld);
+      if (ok) hipLaunchKernelGGL(omega_pack_kernel<double>, dim3(nb(n * k)), dim3(256), 0, s, n, k, Z, zscale, o, ld);
       break;
     }
     case ISVD_FP32: {
       float* o = static_cast<float*>(omega);
       launch_gaussian<float>(n, l, seed, o, ld, s);
-      if (ok) hipLaunchKernelGGL(omega_pack_kernel<float>, dim3(nb(n * k)), dim3(256), 0, s, n, k, Z, o, ld);
+      if (ok) hipLaunchKernelGGL(omega_pack_kernel<float>, dim3(nb(n * k)), dim3(256), 0, s, n, k, Z, zscale, o, ld);
       break;
     }
     default: {
       bf16* o = static_cast<bf16*>(omega);
       launch_gaussian<bf16>(n, l, seed, o, ld, s);
-      if (ok) hipLaunchKernelGGL(omega_pack_kernel<bf16>, dim3(nb(n * k)), dim3(256), 0, s, n, k, Z, o, ld);
+      if (ok) hipLaunchKernelGGL(omega_pack_kernel<bf16>, dim3(nb(n * k)), dim3(256), 0, s, n, k, Z, zscale, o, ld);
       break;
     }
   }

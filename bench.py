@@ -583,7 +583,13 @@ def traffic_summary(args):
                         "bytes_per_launch": round(fk * 1024.0 * f_scale + wk * 1024.0 * w_scale)}
     out = {"workload": cfg.name, "kernel": "spmm_pass_kernel", "spmm_source_sha256_16": spmm_source_hash(),
            "calibration": f"copy kernel of {copy_bytes} bytes: FETCH_SIZE x {f_scale:.5f}, WRITE_SIZE x {w_scale:.5f}",
-           "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5), "passes": passes}
+           "fetch_scale": round(f_scale, 5), "write_scale": round(w_scale, 5), "passes": passes,
+           "note": ("FETCH_SIZE and WRITE_SIZE count the bytes that cross from the L2s to the memory side "
+                    "(Infinity Cache and HBM); they do not separate Infinity-Cache hits from HBM reads"),
+           "commands": [f"rocprofv3 --pmc {c} --output-format csv -d <dir> -o {args.config} -- "
+                        f"python3 bench.py --config {args.config} --products 2 --calibrate-copy"
+                        for c in ("FETCH_SIZE", "WRITE_SIZE")] +
+                       [f"python3 bench.py --config {args.config} --traffic-from <FETCH_SIZE csv> <WRITE_SIZE csv>"]}
     path = traffic_path(args, cfg.name)
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)

@@ -19,7 +19,7 @@ hardware counters when they were taken on the current source.
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload and scales it to one whole iSVD (extrapolated; see its `sample`).
 Other modes: --config c2|c3|c5, --peaks, --products, --traffic-from,
---learners, --dag, --ablation.
+--start-study, --learners, --dag, --ablation.
 """
 
 from __future__ import annotations
@@ -58,6 +58,11 @@ def parse():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="summarise two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE) of a "
                          "--products --calibrate-copy run into profiles/spmm_traffic_<workload>.json (no GPU)")
+    ap.add_argument("--start-study", action="store_true",
+                    help="on the n = 1,000,000 warm-start workload: iterations to rho <= tol from start blocks "
+                         "built from the converged top singular vectors (all, leading, trailing, noisy), from "
+                         "Gaussian rows restricted or weighted by node scores, and from the committed network "
+                         "(one JSON line)")
     ap.add_argument("--oracle-runs", type=int, default=1,
                     help="--config c2/c3: timed runs of the FP64 oracle at fixed q on the GPU's start block "
                          "(median reported; 0 skips it)")
@@ -714,6 +719,88 @@ def headline(args, lib, torch, np):
     print(json.dumps(line), flush=True)
 
 
+def start_study(args, lib, torch, np):
+    """Which start blocks save power iterations on the warm-start workload
+    (n = 1,000,000 Chung-Lu, K = 10, lambda = 0.1, k = 128, p = 16)?  Each
+    start block is passed to the SVD as `omega`; iterations to rho <= tol.
+    V_k comes from a converged run from another seed.  One JSON line."""
+    import math
+    import scipy.sparse as sp
+    from synth import CONFIGS
+    from synth.configs import make_graph
+    cfg = CONFIGS["c5"]
+    g = make_graph(cfg)
+    op = lib.Operator(g, form="ne", coeffs=cfg.coeffs, lam=cfg.lam, precision=lib.FP32)
+    k, p, l, n = cfg.k, cfg.p, cfg.l, g.n
+    kw = dict(tol=args.tol, max_iter=args.max_iter, allow_not_converged=True)
+    res = {}
+
+    def run(name, om):
+        _, _, _, info = op.truncated_svd(k, p, omega=om.contiguous(), **kw)
+        res.setdefault(name, []).append(info.iterations)
+        print(f"[bench] start study: {name}: {info.iterations} iterations, rho {info.residual:.2e}",
+              file=sys.stderr, flush=True)
+
+    gen = torch.Generator(device="cuda")
+
+    def gauss(cols, seed):
+        gen.manual_seed(seed)
+        return torch.randn((n, cols), generator=gen, device="cuda", dtype=torch.float32)
+
+    _, _, V, _ = op.truncated_svd(k, p, seed=77, **kw)
+    V = V.contiguous()
+    sq = math.sqrt(n)            # columns scaled to the norm of the Gaussian ones
+    lev = (V.double() ** 2).sum(1)
+    deg = torch.as_tensor(np.diff(g.indptr).astype(np.float64), device="cuda")
+    a = sp.csr_matrix((np.ones(len(g.indices)), g.indices, g.indptr), shape=(n, n))
+    dd = np.maximum(np.diff(g.indptr), 1).astype(np.float64)
+    tcol = torch.as_tensor(np.sqrt(a.T @ (1.0 / dd ** 2)), device="cuda")
+    for s_ in range(2):
+        run("gaussian", gauss(l, 1000 + s_))
+    run("exact V_k + gaussian p", torch.cat([V * sq, gauss(p, 2000)], 1))
+    for eps in (0.3, 1.0, 3.0):
+        run(f"V_k + noise {eps}", torch.cat([(V + eps * gauss(k, 3000) / sq) * sq, gauss(p, 2000)], 1))
+    for k0 in (16, 32, 64, 96, 112, 120):
+        run(f"exact top {k0} + gaussian", torch.cat([V[:, :k0] * sq, gauss(l - k0, 11 + k0)], 1))
+    for k0 in (64, 96):
+        run(f"exact v_{k0 + 1}..v_{k} + gaussian", torch.cat([V[:, k0:] * sq, gauss(l - (k - k0), 21 + k0)], 1))
+    for sname, score in (("leverage", lev), ("T column norm", tcol), ("degree", deg)):
+        order = torch.argsort(score, descending=True)
+        for H in (256, 1024, 4096, 16384):
+            mask = torch.zeros(n, device="cuda", dtype=torch.float32)
+            mask[order[:H]] = 1.0
+            run(f"gaussian on the top {H} rows by {sname}",
+                torch.cat([mask[:, None] * gauss(k, 7000 + H), gauss(p, 8000)], 1))
+    run("gaussian weighted by sqrt(leverage)", torch.sqrt(lev + 1e-3 * lev.mean()).float()[:, None] * gauss(l, 4000))
+    for a_ in (0.25, 0.5, 1.0):
+        run(f"gaussian weighted by degree^{a_}", (deg + 1.0).pow(a_).float()[:, None] * gauss(l, 5000))
+    try:
+        ws = lib.WarmStart(k, seed=0)
+        ws.set_params(np.load(os.path.join(ROOT, "paper_2111_06312_amd", "weights", "warmstart_k128.npy")))
+        F = lib.features(op)
+        Z = ws.forward(F)
+        Zq, _ = lib.orthonormalize(Z.clone())
+        sv = torch.linalg.svdvals(V.double().T @ Zq.double())
+        span = float((sv ** 2).mean())
+        for s_ in range(3):
+            om, fb = ws.omega(op, F, p, seed=s_)
+            run("learned (orthonormalised)", om)
+        ws.close()
+    except (OSError, ValueError):
+        span = None
+    op.close()
+    pr = 1.0 / (V.double() ** 4).sum(0)
+    order = torch.argsort(deg, descending=True)
+    line = {"metric": "power iterations to rel. residual 1e-4 by start block", "value": res["gaussian"][0],
+            "unit": "iterations", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+            "config": {"workload": cfg.name + "_start_study", "n": n, "k": k, "p": p, "tol": args.tol,
+                       "iterations": res,
+                       "leverage_on_top_0.1pct_by_degree": round(float(lev[order[: n // 1000]].sum()) / k, 3),
+                       "participation_ratio_median": round(float(pr.median()), 1),
+                       "learned_mean_cos2_to_Vk": span}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -744,6 +831,9 @@ def main():
         return
     if args.products:
         products_bench(args, lib, torch, np)
+        return
+    if args.start_study:
+        start_study(args, lib, torch, np)
         return
     if args.learners:
         learners_bench(args, lib, torch, np)

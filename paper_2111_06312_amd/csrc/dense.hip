@@ -1406,8 +1406,7 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* 
           for (int r = 0; r < 4; ++r) {
             const int c = 16 * K + drow<C>(lk, r);
             cs[r] = (rok && c < l) ? static_cast<double>(stored_as<T, C>(q[K][r])) : 0.0;
-  #pragma unroll
-            for (int m = 1; m < 16; m <<= 1) cs[r] += __shfl_xor(cs[r], m, 64);
+            cs[r] = row16_sum(cs[r]);   // DPP: no LDS traffic
           }
           if (li == 0) {
   #pragma unroll
@@ -1491,8 +1490,7 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* 
           for (int r = 0; r < 4; ++r) {
             const int c = 16 * K + drow<C>(lk, r);
             cs[r] = (rok && c < l) ? static_cast<double>(stored_as<T, C>(o[r])) : 0.0;
-#pragma unroll
-            for (int m = 1; m < 16; m <<= 1) cs[r] += __shfl_xor(cs[r], m, 64);
+            cs[r] = row16_sum(cs[r]);   // DPP: no LDS traffic
           }
           if (li == 0) {
 #pragma unroll
@@ -1511,8 +1509,7 @@ __global__ __launch_bounds__(256) void trsm_rows_kernel(int64_t rows, int l, T* 
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             double v = static_cast<double>(csl[J][r]);
-#pragma unroll
-            for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 64);
+            v = row16_sum(v);
             if (li == 0) csw[wave][16 * J + drow<C>(lk, r)] = v;
           }
         }
@@ -1654,8 +1651,7 @@ __global__ __launch_bounds__(64 * W) void trsm_wide_kernel(int64_t rows, T* Y, i
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           cs[r] = rok ? static_cast<double>(stored_as<T, C>(q[K][r])) : 0.0;
-#pragma unroll
-          for (int m = 1; m < 16; m <<= 1) cs[r] += __shfl_xor(cs[r], m, 64);
+          cs[r] = row16_sum(cs[r]);   // DPP: no LDS traffic
         }
         if (li == (K & 15)) {
 #pragma unroll

@@ -154,3 +154,35 @@ def test_committed_weights_against_gaussian_start(gpu_lib):
     assert abs(diff) <= 0.15, (learned, gauss)
     ws.close()
     op.close()
+
+
+def test_learned_start_svd_matches_oracle_from_the_same_start(gpu_lib):
+    """Algorithm 1 from the network's start block (the committed weights):
+    the GPU run and the FP64 oracle run from the same block (the device
+    block read back as FP64) at fixed q agree to 1e-4 in the singular values
+    and 1e-3 rad in the top-k' subspaces."""
+    import os
+    from gpu_helpers import gapped_k
+    from oracle.isvd import isvd as oracle_isvd, principal_angles
+    from oracle.operators import NEDesignMatrix
+    _case("learned start vs oracle")
+    g = chung_lu_graph(6000, 2.5, 12.0, seed=43)
+    K, k, p, q, lam = 10, 128, 16, 3, 0.1
+    coeffs = np.full(K, 1.0 / K)
+    op = gpu_lib.Operator(g, form="ne", coeffs=coeffs, lam=lam, precision=gpu_lib.FP32)
+    ws = gpu_lib.WarmStart(k, seed=0)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    ws.set_params(np.load(os.path.join(root, "paper_2111_06312_amd", "weights", "warmstart_k128.npy")))
+    om, fb = ws.omega(op, gpu_lib.features(op), p, seed=5)
+    assert not fb
+    U, S, V, info = op.truncated_svd(k, p, q=q, omega=om)
+    u, s = to_np(U).astype(np.float64), to_np(S)
+    oop = NEDesignMatrix.from_graph(g, coeffs, lam)
+    uo, so_all, vo = oracle_isvd(oop, k + p, to_np(om).astype(np.float64), q)
+    so = so_all[:k]
+    assert (np.abs(s - so) / so).max() <= 1e-4
+    kk = gapped_k(so_all, k)
+    assert kk > 0
+    assert principal_angles(u[:, :kk], uo[:, :kk]).max() <= 1e-3
+    ws.close()
+    op.close()

@@ -485,8 +485,8 @@ def peaks_bench(args, lib, torch):
     res["infinity_cache_read_gbps"] = round(reps * ic / (ms / 1e3) / 1e9, 1)
     res["infinity_cache_read"] = f"{reps} passes over {ic >> 20} MiB in one launch"
     del buf
-    for name, prec, iters in (("fp64", lib.FP64, 20000), ("fp32", lib.FP32, 20000)):
-        lib.peak_mfma(prec, 100)
+    for name, prec, iters in (("fp64", lib.FP64, 1000), ("fp32", lib.FP32, 2000)):
+        lib.peak_mfma(prec, 20)
         fl, ms = lib.peak_mfma(prec, iters)
         res[f"mfma_{name}_tflops"] = round(fl / (ms / 1e3) / 1e12, 1)
     res["device"] = torch.cuda.get_device_name(0)

@@ -422,7 +422,7 @@ isvd_status isvd_profile_learners_read(double* ms, double* bytes, int64_t* launc
  *    passes); a buffer larger than the L2s and smaller than the Infinity
  *    Cache gives that cache's read rate = reps bytes / time.
  *  isvd_peak_mfma: back-to-back independent MFMAs (16x16x4, FP64 or FP32 by
- *    `precision`), `iters` rounds of eight per wave; *flops receives the
+ *    `precision`), `iters` trips of 32 rounds of eight per wave; *flops receives the
  *    floating-point operations done.
  * Allocate a small device sink per call.  Errors: ISVD_E_INVALID, ISVD_E_HIP. */
 isvd_status isvd_peak_copy(const void* src, void* dst, int64_t bytes, int reps, double* ms, void* stream);

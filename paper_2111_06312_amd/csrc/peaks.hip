@@ -59,6 +59,7 @@ __global__ __launch_bounds__(kPeakThreads) void peak_read_kernel(const uint4* sr
 typedef double v4d_peak __attribute__((ext_vector_type(4)));
 typedef float v4f_peak __attribute__((ext_vector_type(4)));
 constexpr int kPeakChains = 8;   // independent accumulators per wave
+constexpr int kPeakUnroll = 32;  // MFMA rounds per loop trip: the accumulators move between register files once per trip
 
 __global__ __launch_bounds__(kPeakThreads) void peak_mfma_f64_kernel(int64_t iters, double* sink) {
   v4d_peak acc[kPeakChains];
@@ -67,7 +68,9 @@ __global__ __launch_bounds__(kPeakThreads) void peak_mfma_f64_kernel(int64_t ite
   const double a = 1.0 + 1e-9 * threadIdx.x, b = 1.0 - 1e-9 * threadIdx.x;
   for (int64_t it = 0; it < iters; ++it) {
 #pragma unroll
-    for (int c = 0; c < kPeakChains; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+    for (int u = 0; u < kPeakUnroll; ++u)
+#pragma unroll
+      for (int c = 0; c < kPeakChains; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
   }
   double s = 0.0;
 #pragma unroll
@@ -82,7 +85,9 @@ __global__ __launch_bounds__(kPeakThreads) void peak_mfma_f32_kernel(int64_t ite
   const float a = 1.0f + 1e-6f * threadIdx.x, b = 1.0f - 1e-6f * threadIdx.x;
   for (int64_t it = 0; it < iters; ++it) {
 #pragma unroll
-    for (int c = 0; c < kPeakChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+    for (int u = 0; u < kPeakUnroll; ++u)
+#pragma unroll
+      for (int c = 0; c < kPeakChains; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
   }
   float s = 0.f;
 #pragma unroll
@@ -157,7 +162,7 @@ double peak_mfma(bool fp64, int64_t iters, double* sink, double* flops, hipStrea
   ISVD_LAUNCH_CHECK();
   ISVD_HIP(hipEventRecord(ev.b, stream));
   const double waves = static_cast<double>(grid) * (kPeakThreads / 64);
-  *flops = waves * static_cast<double>(iters) * kPeakChains * (16.0 * 16.0 * 4.0 * 2.0);
+  *flops = waves * static_cast<double>(iters) * kPeakUnroll * kPeakChains * (16.0 * 16.0 * 4.0 * 2.0);
   return ev.wait_ms();
 }
 

@@ -602,6 +602,16 @@ def traffic_summary(args):
     print(json.dumps(out))
 
 
+def phase_summary(lib, steps, mean_step_s):
+    """Per-step seconds of each phase of Algorithm 1 recorded since profiling
+    was enabled (event-timed on the SVD's stream), and the rest of the step."""
+    ph = lib.profile_phases_read()
+    out = {name: round(ms / 1e3 / max(steps, 1), 4) for name, (ms, _) in ph.items()}
+    out["between_phases"] = round(mean_step_s - sum(out.values()), 4)
+    out["occurrences_per_step"] = {name: n // max(steps, 1) for name, (_, n) in ph.items()}
+    return out
+
+
 def headline(args, lib, torch, np):
     """The default line: the n = 2,000,000 NE workload with FP32 blocks to
     rho <= tol (`value`), the BF16-storage form beside it, and the errors of
@@ -637,6 +647,7 @@ def headline(args, lib, torch, np):
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
     roof32 = pass_roofline(lib, lib.FP32, HBM_PEAK_GBPS, "hbm", args, cfg.name, total)
+    phases32 = phase_summary(lib, len(times), sum(times) / len(times))
     lib.profile_spmm_read()
     lib.profile_spmm(False)
 
@@ -660,6 +671,7 @@ def headline(args, lib, torch, np):
     total16 = time.perf_counter() - tb
     roof16 = pass_roofline(lib, lib.BF16, HBM_PEAK_GBPS, "hbm", args, cfg.name, total16)
     roof16_f = pass_roofline(lib, lib.FP32, HBM_PEAK_GBPS, "hbm", args, cfg.name, total16)
+    phases16 = phase_summary(lib, len(t16), sum(t16) / len(t16)) if t16 else None
     lib.profile_spmm_read()
     lib.profile_spmm(False)
     mean32 = sum(times) / len(times)
@@ -668,7 +680,7 @@ def headline(args, lib, torch, np):
             "speedup_vs_fp32": round(mean32 / mean16, 3) if mean16 else None,
             "iterations": [i.iterations for i in i16], "bf16_iterations": [i.bf16_iterations for i in i16],
             "residual": [i.residual for i in i16], "converged": all(i.status == 0 for i in i16),
-            "roofline_bf16_passes": roof16, "roofline_fp32_finish_passes": roof16_f}
+            "roofline_bf16_passes": roof16, "roofline_fp32_finish_passes": roof16_f, "phases_s": phases16}
 
     errors = None
     if not args.no_errors:
@@ -708,7 +720,7 @@ def headline(args, lib, torch, np):
                    "iterations": [i.iterations for i in infos], "applies": [i.applies for i in infos],
                    "residual": [i.residual for i in infos], "converged": converged,
                    "median_step_s": round(statistics.median(times), 4), "start_block": "gaussian",
-                   "bf16_storage": bf16, "errors_vs_fp64": errors},
+                   "phases_s": phases32, "bf16_storage": bf16, "errors_vs_fp64": errors},
         "roofline": roof32,
     }
     if not args.no_cpu_baseline:
@@ -924,6 +936,7 @@ def main():
         bound = "infinity-cache"
         peak = infinity_cache_peak()
     roof = pass_roofline(lib, precision, peak, bound, args, cfg.name, total)
+    phases = phase_summary(lib, len(times), sum(times) / len(times))
     lib.profile_spmm_read()
     lib.profile_spmm(False)
     ms_per_step = 1e3 * total / args.steps
@@ -947,7 +960,7 @@ def main():
                    "iterations": [i.iterations for i in infos], "applies": [i.applies for i in infos],
                    **({"bf16_iterations": [i.bf16_iterations for i in infos]} if precision == lib.BF16 else {}),
                    "residual": [i.residual for i in infos], "converged": converged,
-                   "median_step_s": round(statistics.median(times), 4),
+                   "median_step_s": round(statistics.median(times), 4), "phases_s": phases,
                    "start_block": "learned warm start" if ws is not None else "gaussian",
                    **({"gaussian_start": gauss, "warmstart_fallbacks": fallbacks,
                        "warmstart_weights": os.path.relpath(args.warmstart, ROOT)} if ws is not None else {})},

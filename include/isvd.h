@@ -386,8 +386,8 @@ isvd_status isvd_nc_fit(int64_t rows_u, int64_t rows_v, int64_t k, int64_t ny, i
 /* on != 0: from now on every sparse pass is bracketed by a hipEvent pair on
  * its launch stream (two event records per pass, no host synchronisation; the
  * byte counts come from the host copy of the CSR sizes), and so are the
- * kernels of each learner call; the records are cleared.  on == 0 stops
- * recording. */
+ * kernels of each learner call and the phases of each truncated SVD; the
+ * records are cleared.  on == 0 stops recording. */
 isvd_status isvd_profile_spmm_enable(int on);
 
 /* Totals over the passes recorded since the last enable/read (host outputs):
@@ -410,6 +410,17 @@ isvd_status isvd_profile_spmm_read_storage(isvd_precision storage, double* total
  * algorithmic bytes (U, V, Y rows read once per use, outputs written once,
  * indices), number of calls.  Waits for the events; clears the records. */
 isvd_status isvd_profile_learners_read(double* ms, double* bytes, int64_t* launches);
+
+/* Phases of the truncated SVDs run since the last enable/read (host arrays
+ * of 5): [0] the products with M and M^T (Algorithm 1's applies), [1]
+ * orthonormalisation (Gram, Cholesky, triangular solve; Algorithm 2),
+ * [2] Rayleigh-Ritz (the small SVD), [3] residual checks, [4] the output
+ * products U = Q Z, V = Q U.  ms[i]: summed durations between hipEvents
+ * recorded on the SVD's stream before and after each occurrence; count[i]:
+ * occurrences.  Time between phases (start block, storage switch, host
+ * waits) is in none of them.  Waits for the events; clears the records.
+ * Errors: ISVD_E_INVALID (null output). */
+isvd_status isvd_profile_phases_read(double* ms, int64_t* count);
 
 /* Peak rates of the device, for the rooflines of the kernels above (not
  * steps of the method).  Each call enqueues its kernels between a hipEvent

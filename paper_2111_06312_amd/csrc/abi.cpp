@@ -644,8 +644,19 @@ isvd_status isvd_profile_spmm_enable(int on) {
 isvd_status isvd_profile_learners_read(double* ms, double* bytes, int64_t* launches) {
   return guarded([&]() -> isvd_status {
     ISVD_CHECK(ms && bytes && launches, ISVD_E_INVALID, "null output");
-    for (int c = 1; c < kProfileClasses; ++c)
+    for (int c = 1; c <= kLearnerClasses; ++c)
       profile_read(c, ms + c - 1, bytes + c - 1, nullptr, launches + c - 1);
+    return ISVD_OK;
+  });
+}
+
+isvd_status isvd_profile_phases_read(double* ms, int64_t* count) {
+  return guarded([&]() -> isvd_status {
+    ISVD_CHECK(ms && count, ISVD_E_INVALID, "null output");
+    for (int i = 0; i < kPhaseCount; ++i) {
+      double bytes = 0.0;
+      profile_read(kPhaseFirst + i, ms + i, &bytes, nullptr, count + i);
+    }
     return ISVD_OK;
   });
 }

@@ -88,6 +88,14 @@ void trace_check(const SvdState& st, const char* phase, int t) {
 
 // Cholesky flags (see launch_cholesky): zeroed once per call, read (with a
 // stream synchronisation) only where the host needs them.
+// Event bracket of one phase while profiling is on (null token otherwise).
+void* phase_begin(Phase ph, hipStream_t stream) {
+  return spmm_profiling() ? profile_begin(ph, stream, 0.0, 0.0) : nullptr;
+}
+void phase_end(hipStream_t stream, void* tok) {
+  if (tok) profile_end(stream, tok);
+}
+
 void clear_chol_flags(SvdState& st, hipStream_t stream) {
   st.flag.ensure(4 * sizeof(int));
   ISVD_HIP(hipMemsetAsync(st.flag.p, 0, 4 * sizeof(int), stream));
@@ -272,6 +280,7 @@ void finalize(SvdState& st, isvd_operator* op, void* U, int64_t ldu, double* S, 
   using C = typename ComputeOf<T>::type;
   using CO = typename ComputeOf<O>::type;
   const int l = st.l, k = st.k;
+  void* tok = phase_begin(kPhaseOutput, stream);
   DevBuf zb, ub, uo, vo;
   zb.ensure(static_cast<size_t>(l) * k * sizeof(C));
   ub.ensure(static_cast<size_t>(l) * k * sizeof(C));
@@ -296,6 +305,7 @@ void finalize(SvdState& st, isvd_operator* op, void* U, int64_t ldu, double* S, 
                             static_cast<float*>(V), ldv, 1.0, 0.0, GemmEpi::Store, nullptr, nullptr, stream);
     ISVD_HIP(hipStreamSynchronize(stream));
   }
+  phase_end(stream, tok);
   ISVD_HIP(hipMemcpyAsync(S, st.sig.p, k * sizeof(double), hipMemcpyDeviceToDevice, stream));
   ISVD_HIP(hipStreamSynchronize(stream));
   (void)op;
@@ -381,10 +391,14 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
   bool qc_sums = false;  // sum_c holds 1^T Qc (false for the start block)
   for (int t = t0;; ++t) {
     T* Y = st.y.as<T>();
+    void* tok = phase_begin(kPhaseProduct, stream);
     apply_operator<T>(op, false, st.qc.as<T>(), st.ld, l, Y, st.ld, stream, qc_sums ? st.sum_c.as<double>() : nullptr);
+    phase_end(stream, tok);
     st.applies++;
     if (!fixed && st.have_ritz && st.ritz_iter == t - 1) {
+      tok = phase_begin(kPhaseCheck, stream);
       st.residual = residual<T>(st, Y, stream);
+      phase_end(stream, tok);
       trace_check(st, std::is_same<T, bf16>::value ? "bf16" : (std::is_same<T, float>::value ? "fp32" : "fp64"), t - 1);
       if (st.residual <= tol) {
         st.iterations = t - 1;
@@ -414,7 +428,9 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
     if (!fixed && t >= prm->max_iter) {
       // out of iterations: return the triplets of the last finished iteration
       if (st.ritz_iter != t - 1 && t >= 1) {
+        tok = phase_begin(kPhaseRitz, stream);
         ritz(st, stream, kRitzTol<T>);
+        phase_end(stream, tok);
         st.ritz_iter = t - 1;
       }
       st.iterations = t - 1;
@@ -425,24 +441,30 @@ int run_phase(SvdState& st, isvd_operator* op, const isvd_svd_params* prm, doubl
     const bool ritz_now = fixed ? (t >= prm->q)
                                 : (t >= sched.next || (phase_cap > 0 && t + 1 >= phase_cap) || t + 1 >= prm->max_iter);
     const int np_ = ritz_now || prm->orth_passes >= 2 ? 2 : 1;
+    tok = phase_begin(kPhaseOrth, stream);
     orthonormalize<T>(st, Y, st.r, nullptr, ne ? st.sum_r.as<double>() : nullptr, stream, np_);
+    phase_end(stream, tok);
     std::swap(st.qr.p, st.y.p);
     std::swap(st.qr.bytes, st.y.bytes);
+    tok = phase_begin(kPhaseProduct, stream);
     apply_operator<T>(op, true, st.qr.as<T>(), st.ld, l, st.w.as<T>(), st.ld, stream, ne ? st.sum_r.as<double>() : nullptr);
+    phase_end(stream, tok);
     st.applies++;
+    tok = phase_begin(kPhaseOrth, stream);
     orthonormalize<T>(st, st.w.as<T>(), st.c, st.Rc.as<double>(), ne ? st.sum_c.as<double>() : nullptr, stream, np_);
+    phase_end(stream, tok);
     std::swap(st.qc.p, st.w.p);
     std::swap(st.qc.bytes, st.w.bytes);
     qc_sums = ne;
-    if (fixed && t >= prm->q) {
+    if ((fixed && t >= prm->q) || (!fixed && ritz_now)) {
+      tok = phase_begin(kPhaseRitz, stream);
       ritz(st, stream, kRitzTol<T>);
+      phase_end(stream, tok);
       st.ritz_iter = t;
+    }
+    if (fixed && t >= prm->q) {
       st.iterations = t;
       return 1;
-    }
-    if (!fixed && ritz_now) {
-      ritz(st, stream, kRitzTol<T>);
-      st.ritz_iter = t;
     }
   }
 }

@@ -56,8 +56,14 @@ void spmm_profile_read(double* ms, double* gather, double* compulsory, int64_t* 
                        bool clear = true);
 
 // Timed regions of other kernels (classes 1 .. kProfileClasses - 1), recorded
-// while spmm_profiling() is on.
-constexpr int kProfileClasses = 4;
+// while spmm_profiling() is on: classes 1..3 the learner calls, classes
+// kPhaseFirst.. the phases of a truncated SVD (the products with M and M^T,
+// orthonormalisation, Rayleigh-Ritz, residual checks, the output products).
+constexpr int kLearnerClasses = 3;
+constexpr int kPhaseFirst = 1 + kLearnerClasses;
+enum Phase { kPhaseProduct = kPhaseFirst, kPhaseOrth, kPhaseRitz, kPhaseCheck, kPhaseOutput };
+constexpr int kPhaseCount = 5;
+constexpr int kProfileClasses = kPhaseFirst + kPhaseCount;
 void* profile_begin(int cls, hipStream_t stream, double bytes, double bytes2, int tag = 0);
 void profile_end(hipStream_t stream, void* token);
 void profile_read(int cls, double* ms, double* bytes, double* bytes2, int64_t* launches, int tag = 0,

@@ -441,6 +441,19 @@ def profile_spmm_read_storage(precision):
     return ms.value, gb.value, cb.value, n.value
 
 
+PHASES = ("products", "orthonormalisation", "rayleigh_ritz", "residual_checks", "output_products")
+
+
+def profile_phases_read():
+    """{phase: (ms, occurrences)} of the truncated SVDs since profiling was
+    enabled or last read (event-timed on the SVD's stream); clears them."""
+    load()
+    ms = (ct.c_double * len(PHASES))()
+    n = (ct.c_int64 * len(PHASES))()
+    _check(_lib.isvd_profile_phases_read(ct.cast(ms, ct.c_void_p), ct.cast(n, ct.c_void_p)))
+    return {name: (ms[i], n[i]) for i, name in enumerate(PHASES)}
+
+
 def peak_copy(src, dst, reps=1):
     """Time `reps` device copies src -> dst (same byte size, 16-byte
     aligned) with the library's copy kernel; returns milliseconds."""

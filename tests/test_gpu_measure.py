@@ -1,6 +1,9 @@
 """Measurement entry points on the GPU: the peak-rate probes (a copy that
 really copies, positive times, the MFMA flop count) and the per-storage
-record of sparse passes (a BF16 operator's passes recorded as BF16)."""
+record of sparse passes (a BF16 operator's passes recorded as BF16), and
+the phase record of a truncated SVD."""
+
+import time
 
 import numpy as np
 import pytest
@@ -50,3 +53,30 @@ def test_profile_records_passes_by_storage(gpu_lib):
     assert n16 == 2 * K and n32 == 0 and ms32 == 0.0
     assert n == n16 and gb == gb16 and cb == cb16 and ms == ms16
     assert gb16 > cb16 > 0.0
+
+
+def test_phase_profile_covers_the_steps_of_a_truncated_svd(gpu_lib):
+    print_case("phase profile")
+    g = chung_lu_graph(4000, 2.5, 8.0, seed=5)
+    op = gpu_lib.Operator(g, form="ne", coeffs=np.full(3, 1.0 / 3), lam=0.05, precision=gpu_lib.FP32)
+    gpu_lib.profile_spmm(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, info = op.truncated_svd(8, 8, tol=1e-4, max_iter=300, seed=2)
+    torch.cuda.synchronize()
+    wall_ms = 1e3 * (time.perf_counter() - t0)
+    ph = gpu_lib.profile_phases_read()
+    gpu_lib.profile_spmm(False)
+    assert set(ph) == set(gpu_lib.PHASES)
+    # one product with M and one with M^T per iteration, plus the product that
+    # feeds the last residual check
+    assert ph["products"][1] == info.applies
+    assert ph["orthonormalisation"][1] >= 2 * info.iterations
+    assert ph["rayleigh_ritz"][1] == info.ritz_steps
+    assert ph["residual_checks"][1] >= 1
+    assert ph["output_products"][1] == 1
+    total = sum(ms for ms, _ in ph.values())
+    assert 0.0 < total <= wall_ms
+    # read clears the record
+    assert all(n == 0 for _, n in gpu_lib.profile_phases_read().values())
+    op.close()

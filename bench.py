@@ -706,6 +706,29 @@ def headline(args, lib, torch, np):
             del U
             print(f"[bench] error run {name}: {errors[name]}", file=sys.stderr, flush=True)
         del U64, om
+        # at the tolerance: each storage's own run to rho <= tol (BF16 with its FP32
+        # finish) against an FP64 run to rho <= tol, all from the same seed's draws
+        op64 = mk(lib.FP64)
+        te = time.perf_counter()
+        U64, S64, _, i64 = op64.truncated_svd(cfg.k, cfg.p, seed=7, allow_not_converged=True, **kw)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - te
+        op64.close()
+        del op64
+        s64 = S64.cpu().numpy()
+        kk = gapped_k(s64, cfg.k)
+        at_tol = {"seed": 7, "fp64_s": round(t64, 3), "fp64_iterations": i64.iterations,
+                  "fp64_residual": i64.residual, "k_gapped": kk}
+        for name, op, kwx in (("fp32", op32, kw), ("bf16", op16, kw16)):
+            U, S, _, inf = op.truncated_svd(cfg.k, cfg.p, seed=7, allow_not_converged=True, **kwx)
+            s = S.cpu().numpy()
+            at_tol[name] = {"sigma_max_rel_err": float(np.max(np.abs(s - s64) / s64)),
+                            "subspace_angle_rad": subspace_angle(torch, U64, U, kk),
+                            "iterations": inf.iterations, "residual": inf.residual}
+            del U
+            print(f"[bench] error run at tol {name}: {at_tol[name]}", file=sys.stderr, flush=True)
+        errors["at_tolerance"] = at_tol
+        del U64
     op16.close()
 
     converged = all(i.status == 0 for i in infos)

@@ -55,6 +55,10 @@ def parse():
     ap.add_argument("--products", type=int, default=0,
                     help="time this many product pairs (M Y, M^T Y) per block storage (FP32, BF16) on the "
                          "workload's operator instead of whole SVDs (a short run for hardware counters)")
+    ap.add_argument("--orth", type=int, default=0,
+                    help="time this many orthonormalisations (CholeskyQR2: two passes of Gram, Cholesky, "
+                         "triangular solve) of an n x l Gaussian block of the workload's shape per block "
+                         "storage (FP32, BF16) instead of whole SVDs (a short run for hardware counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="summarise two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE) of a "
                          "--products --calibrate-copy run into profiles/spmm_traffic_<workload>.json (no GPU)")
@@ -497,6 +501,44 @@ def peaks_bench(args, lib, torch):
     print(json.dumps(line), flush=True)
 
 
+def orth_bench(args, lib, torch):
+    """`--orth` orthonormalisations (CholeskyQR2: Algorithm 2's Cholesky QR
+    run twice, each pass a Gram, a Cholesky and a triangular solve) per block
+    storage on an n x l block of the workload's shape, after one warm-up; one
+    JSON line with the time per call (HIP events around each call) and the
+    orthogonality of the result."""
+    from synth import CONFIGS
+    cfg = CONFIGS[args.config]
+    n, l = cfg.n, cfg.l
+    res = {}
+    for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16)):
+        y0 = lib.gaussian_block(n, l, seed=3, dtype=torch.float64)
+        y0 = (y0 * torch.logspace(0, 3, l, dtype=torch.float64, device="cuda")[None, :]).to(dt)
+        y = y0.clone()
+        lib.orthonormalize(y)
+        torch.cuda.synchronize()
+        ms = 0.0
+        for _ in range(args.orth):
+            y.copy_(y0)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
+            lib.orthonormalize(y)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms += ev[0].elapsed_time(ev[1])
+        qd = y.double()
+        orth_err = float((qd.T @ qd - torch.eye(l, dtype=torch.float64, device="cuda")).abs().max())
+        res[name] = {"ms_per_call": round(ms / args.orth, 3), "orthogonality": orth_err}
+        print(f"[bench] orth {name}: {res[name]}", file=sys.stderr, flush=True)
+        del y0, y, qd
+    line = {"metric": "CholeskyQR2 time per block (two passes of Gram, Cholesky, triangular solve)",
+            "value": res["fp32"]["ms_per_call"],
+            "unit": "ms", "n_gpus": 1, "steps": args.orth, "higher_is_better": False, "data": "synthetic",
+            "config": {"workload": f"{cfg.name}_orth", "n": n, "l": l,
+                       "block": "Gaussian columns scaled by 10^(3 j / (l - 1))", **res}}
+    print(json.dumps(line), flush=True)
+
+
 def products_bench(args, lib, torch, np):
     """`--products` pairs (M Y then M^T Y) per block storage on the workload's
     operator, after one warm-up pair; one JSON line with the sparse-pass
@@ -866,6 +908,9 @@ def main():
         return
     if args.products:
         products_bench(args, lib, torch, np)
+        return
+    if args.orth:
+        orth_bench(args, lib, torch)
         return
     if args.start_study:
         start_study(args, lib, torch, np)

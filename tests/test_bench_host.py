@@ -27,7 +27,8 @@ def test_new_modes_are_listed_in_help():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 0
-    for flag in ("--peaks", "--products", "--traffic-from", "--bf16-steps", "--oracle-runs", "--calibrate-copy"):
+    for flag in ("--peaks", "--products", "--orth", "--traffic-from", "--bf16-steps", "--oracle-runs",
+                 "--calibrate-copy", "--start-study"):
         assert flag in r.stdout
 
 

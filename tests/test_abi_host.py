@@ -42,6 +42,7 @@ def test_argument_errors_are_reported_without_a_gpu(lib):
     assert lib.isvd_truncated_svd(None, None, None, 0, None, None, 0, None, None) == isvd.ISVD_E_INVALID
     assert lib.isvd_matmul_block(None, 0, None, 1, 1, None, 1, None) == isvd.ISVD_E_INVALID
     assert lib.isvd_small_svd(0, None, None, None, None, None) == isvd.ISVD_E_INVALID
+    assert lib.isvd_profile_phases_read(None, None) == isvd.ISVD_E_INVALID
     lib.isvd_destroy_operator(None)
 
 

@@ -86,3 +86,20 @@ def test_gapped_k_and_subspace_helpers():
     b = a.clone()
     b[1, 1], b[2, 1] = np.cos(th), np.sin(th)
     assert abs(bench.subspace_angle(torch, a, b, 2) - th) < 1e-12
+
+
+def test_phase_summary_per_step_and_remainder():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    class FakeLib:
+        @staticmethod
+        def profile_phases_read():
+            return {"products": (8000.0, 390), "orthonormalisation": (1200.0, 388), "rayleigh_ritz": (50.0, 14),
+                    "residual_checks": (80.0, 14), "output_products": (10.0, 2)}
+
+    out = bench.phase_summary(FakeLib, 2, 4.8)
+    assert out["products"] == 4.0 and out["orthonormalisation"] == 0.6
+    assert out["occurrences_per_step"]["products"] == 195
+    # the rest of the step: 4.8 - (4.0 + 0.6 + 0.025 + 0.04 + 0.005)
+    assert abs(out["between_phases"] - 0.13) < 1e-9

@@ -13,6 +13,7 @@
 #include <mutex>
 #include <tuple>
 #include <type_traits>
+#include <vector>
 
 namespace isvd {
 
@@ -43,7 +44,8 @@ __device__ inline C ld_as(const T* p) { return static_cast<C>(Elem<T>::load(p));
 // so one k-step reads three A and three B fragments for up to nine MFMAs.
 // For A^T A only blocks on or above the diagonal exist and tiles below the
 // diagonal inside a diagonal block are skipped.  A workgroup holds up to 16
-// waves (jobs) and streams one row slice through two LDS buffers (rows staged
+// waves (jobs; for A^T A a whole number of waves per SIMD, jobs placed on the
+// SIMDs by cost) and streams one row slice through two LDS buffers (rows staged
 // as FP32 for FP32/BF16 inputs, FP64 otherwise): the next chunk is loaded
 // into registers while the MFMAs of the current one run, one barrier per
 // chunk.  Row slices write partial tiles that a second kernel adds in a
@@ -55,6 +57,14 @@ constexpr int kGramPF = 16;         // staged elements per thread per chunk
 constexpr int kGramMaxParts = 256;
 constexpr int kGramMinStageWaves = 8;
 constexpr size_t kGramMaxLds = 96 * 1024;
+constexpr int kGramTableSlots = 64;   // wave slots (groups x waves) a job table can describe
+
+// Job of each wave slot (group * waves + wave) when the plan balances the
+// work of A^T A over the SIMDs (0xff: no job); passed by value.
+struct GramJobTable {
+  uint8_t bi[kGramTableSlots];
+  uint8_t bj[kGramTableSlots];
+};
 
 template <typename TA, typename TB>
 struct GramStage {
@@ -193,7 +203,8 @@ constexpr int gram_rows_per_wave() {
 template <typename TA, typename TB, int CS, int VW, bool SAME, int KSPLIT>
 __global__ __launch_bounds__(64 * kGramMaxWaves) void gram_partial_kernel(
     int64_t rows, int m, int p, const TA* A, int64_t lda, const TB* B, int64_t ldb, int tm, int tp, int nbi,
-    int nbj, int njobs, int64_t rows_per_block, int rb, int ldsa, int ldsb, double* partial, int mp, int pp) {
+    int nbj, int njobs, int64_t rows_per_block, int rb, int ldsa, int ldsb, double* partial, int mp, int pp,
+    int use_table, GramJobTable table) {
   using S = typename GramStage<TA, TB>::type;
   constexpr int J = gram_rows_per_wave<S, CS, VW, SAME>();
   extern __shared__ __align__(16) unsigned char gram_smem[];
@@ -206,10 +217,15 @@ __global__ __launch_bounds__(64 * kGramMaxWaves) void gram_partial_kernel(
   // KSPLIT == 2: waves wv and wv + nj share job wv, each taking half the k-steps
   const int nj = nw / KSPLIT, set = KSPLIT == 1 ? 0 : wv / nj;
   const int job = static_cast<int>(blockIdx.y) * nj + (wv - set * nj);
-  const bool has_job = job < njobs;
-  // job -> block (bi, bj): upper triangle row by row for A^T A, else row-major
+  bool has_job = job < njobs;
+  // job -> block (bi, bj): from the plan's table, else the upper triangle row
+  // by row for A^T A and row-major otherwise
   int bi = 0, bj = 0;
-  if (has_job) {
+  if (use_table) {
+    has_job = table.bi[job] != 0xff;
+    bi = has_job ? table.bi[job] : 0;
+    bj = has_job ? table.bj[job] : 0;
+  } else if (has_job) {
     if (SAME) {
       int rest = job;
       while (rest >= nbj - bi) {
@@ -381,7 +397,103 @@ struct GramPlan {
   int mp, pp, tm, tp, nbi, nbj, njobs, waves, groups, vw, cs, rb, ldsa, ldsb, nparts, ksplit;
   int64_t rows_per_block;
   size_t lds;
+  bool use_table = false;
+  GramJobTable table{};
 };
+
+// Balanced placement of the jobs of A^T A.  Waves w, w + 4, w + 8, ... of a
+// workgroup share one SIMD, and a workgroup takes as long as its busiest
+// SIMD; diagonal blocks cost kGramRB (kGramRB + 1) / 2 MFMAs per k-step,
+// the others kGramRB^2.  The plan chooses how many jobs of each kind every
+// group holds and spreads them over the group's four SIMDs so that the sum
+// over groups of the busiest SIMD's cost is least (exhaustive over the two
+// job kinds; every group has `waves` slots, a multiple of four).
+void balance_gram_jobs(GramPlan& g) {
+  const int nb = g.nbi, k = g.waves / 4, G = g.groups;
+  const int cd = kGramRB * (kGramRB + 1) / 2, co = kGramRB * kGramRB;
+  const int nd = nb, no = g.njobs - nb;
+  // best split of (o, d) jobs over four bins of k slots: least maximum bin cost
+  auto bins = [&](int o, int d, int (&bo)[4], int (&bd)[4]) {
+    int best = -1;
+    for (int o0 = 0; o0 <= std::min(o, k); ++o0)
+      for (int o1 = 0; o1 <= std::min(o - o0, k); ++o1)
+        for (int o2 = 0; o2 <= std::min(o - o0 - o1, k); ++o2) {
+          const int o3 = o - o0 - o1 - o2;
+          if (o3 > k) continue;
+          int oo[4] = {o0, o1, o2, o3}, dd[4] = {0, 0, 0, 0};
+          bool ok = true;
+          for (int x = 0; x < d; ++x) {   // each diagonal job to the cheapest bin with room
+            int tgt = -1;
+            for (int b = 0; b < 4; ++b)
+              if (oo[b] + dd[b] < k && (tgt < 0 || co * oo[b] + cd * dd[b] < co * oo[tgt] + cd * dd[tgt])) tgt = b;
+            if (tgt < 0) {
+              ok = false;
+              break;
+            }
+            ++dd[tgt];
+          }
+          if (!ok) continue;
+          int mx = 0;
+          for (int b = 0; b < 4; ++b) mx = std::max(mx, co * oo[b] + cd * dd[b]);
+          if (best < 0 || mx < best) {
+            best = mx;
+            for (int b = 0; b < 4; ++b) {
+              bo[b] = oo[b];
+              bd[b] = dd[b];
+            }
+          }
+        }
+    return best;
+  };
+  // cost[g][o][d]: least sum of busiest-SIMD costs for groups g.. holding o and d jobs
+  const int INF = 1 << 30;
+  std::vector<int> cost((G + 1) * (no + 1) * (nd + 1), INF), pick_o(cost.size(), 0), pick_d(cost.size(), 0);
+  auto at = [&](int gg, int o, int d) { return (gg * (no + 1) + o) * (nd + 1) + d; };
+  cost[at(G, 0, 0)] = 0;
+  for (int gg = G - 1; gg >= 0; --gg)
+    for (int o = 0; o <= no; ++o)
+      for (int d = 0; d <= nd; ++d)
+        for (int og = 0; og <= std::min(o, 4 * k); ++og)
+          for (int dg = 0; dg <= std::min(d, 4 * k - og); ++dg) {
+            const int rest = cost[at(gg + 1, o - og, d - dg)];
+            if (rest >= INF) continue;
+            int bo[4], bd[4];
+            const int c = bins(og, dg, bo, bd);
+            if (c < 0 || c + rest >= cost[at(gg, o, d)]) continue;
+            cost[at(gg, o, d)] = c + rest;
+            pick_o[at(gg, o, d)] = og;
+            pick_d[at(gg, o, d)] = dg;
+          }
+  if (cost[at(0, no, nd)] >= INF) return;
+  // job lists in the row-by-row order of the upper triangle
+  std::vector<std::pair<int, int>> diag, off;
+  for (int bi = 0; bi < nb; ++bi)
+    for (int bj = bi; bj < nb; ++bj) (bi == bj ? diag : off).push_back({bi, bj});
+  for (int e = 0; e < kGramTableSlots; ++e) g.table.bi[e] = g.table.bj[e] = 0xff;
+  size_t io = 0, id = 0;
+  int o = no, d = nd;
+  for (int gg = 0; gg < G; ++gg) {
+    const int og = pick_o[at(gg, o, d)], dg = pick_d[at(gg, o, d)];
+    int bo[4], bd[4];
+    bins(og, dg, bo, bd);
+    for (int b = 0; b < 4; ++b) {
+      int slot = 0;
+      for (int x = 0; x < bo[b]; ++x, ++slot) {
+        const int e = gg * g.waves + b + 4 * slot;
+        g.table.bi[e] = static_cast<uint8_t>(off[io].first);
+        g.table.bj[e] = static_cast<uint8_t>(off[io++].second);
+      }
+      for (int x = 0; x < bd[b]; ++x, ++slot) {
+        const int e = gg * g.waves + b + 4 * slot;
+        g.table.bi[e] = static_cast<uint8_t>(diag[id].first);
+        g.table.bj[e] = static_cast<uint8_t>(diag[id++].second);
+      }
+    }
+    o -= og;
+    d -= dg;
+  }
+  g.use_table = true;
+}
 
 // Row slices: at most kGramMaxParts (one per CU), each a multiple of 16 rows
 // (at least 64), so that large blocks use every CU.
@@ -428,6 +540,26 @@ GramPlan plan_gram(int64_t rows, int m, int p, bool same, int esize, bool paired
   // halves of every chunk's k-steps, and their sums meet in LDS at the end.
   g.ksplit = (same && g.cs <= 4 && g.groups == 1 && g.njobs % 4 != 0 && 2 * g.njobs <= kGramMaxWaves) ? 2 : 1;
   g.waves *= g.ksplit;
+  // A^T A with one wave per job: whole SIMD rows of waves, jobs placed by cost
+  // (the placement depends only on the block count and the group shape, so it
+  // is worked out once per shape)
+  if (same && g.ksplit == 1) {
+    const int w4 = static_cast<int>(round_up(ceil_div(g.njobs, g.groups), 4));
+    if (g.groups * w4 <= kGramTableSlots) {
+      g.waves = w4;
+      static std::mutex mu;
+      static std::map<std::tuple<int, int, int>, std::pair<bool, GramJobTable>> placed;
+      std::lock_guard<std::mutex> lk(mu);
+      const auto key = std::make_tuple(g.nbi, g.waves, g.groups);
+      auto it = placed.find(key);
+      if (it == placed.end()) {
+        balance_gram_jobs(g);
+        it = placed.emplace(key, std::make_pair(g.use_table, g.table)).first;
+      }
+      g.use_table = it->second.first;
+      g.table = it->second.second;
+    }
+  }
   // A^T B with few jobs (a narrow B): waves without a job still stage rows,
   // so that each chunk is deep enough to hide the load latency
   if (!same && g.groups == 1 && g.waves < kGramMinStageWaves) g.waves = kGramMinStageWaves;
@@ -460,7 +592,7 @@ void gram_launch(const GramPlan& g, int64_t rows, int m, int p, const TA* A, int
     if (g.ksplit == 2) {
       hipLaunchKernelGGL((gram_partial_kernel<TA, TB, CS, VW, SAME, 2>), dim3(g.nparts, g.groups), dim3(64 * g.waves),
                          g.lds, stream, rows, m, p, A, lda, B, ldb, g.tm, g.tp, g.nbi, g.nbj, g.njobs,
-                         g.rows_per_block, g.rb, g.ldsa, g.ldsb, work, g.mp, g.pp);
+                         g.rows_per_block, g.rb, g.ldsa, g.ldsb, work, g.mp, g.pp, 0, g.table);
       ISVD_LAUNCH_CHECK();
       return;
     }
@@ -468,7 +600,7 @@ void gram_launch(const GramPlan& g, int64_t rows, int m, int p, const TA* A, int
   ISVD_CHECK(g.ksplit == 1, ISVD_E_INVALID, "gram: split jobs need a small A^T A");
   hipLaunchKernelGGL((gram_partial_kernel<TA, TB, CS, VW, SAME, 1>), dim3(g.nparts, g.groups), dim3(64 * g.waves),
                      g.lds, stream, rows, m, p, A, lda, B, ldb, g.tm, g.tp, g.nbi, g.nbj, g.njobs, g.rows_per_block,
-                     g.rb, g.ldsa, g.ldsb, work, g.mp, g.pp);
+                     g.rb, g.ldsa, g.ldsb, work, g.mp, g.pp, g.use_table ? 1 : 0, g.table);
   ISVD_LAUNCH_CHECK();
 }
 

@@ -39,7 +39,11 @@ def test_device_gaussian_matches_oracle_philox(gpu_lib):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
 @pytest.mark.parametrize("rows,m", [(1, 3), (1000, 42), (64, 80), (777, 17), (70001, 144), (5000, 288),
-                                    (3001, 600)])
+                                    (3001, 600),
+                                    # job placements of A^T A: one group of 10 and 15 jobs, two of 21,
+                                    # three of 36 and 45, four of 55 (a whole number of waves per SIMD)
+                                    (20000, 192), (9000, 240), (20000, 256), (5000, 384), (3000, 432),
+                                    (3000, 480)])
 def test_gram_exact_products_fp64_sums(gpu_lib, dtype, rows, m):
     _print_case("gram", dtype, rows, m)
     y = gaussian_block(rows, m, seed=rows + m)

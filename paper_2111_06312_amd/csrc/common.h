@@ -123,6 +123,28 @@ __device__ inline double row16_sum(double v) {
   return v;
 }
 
+// Four sums over the 16 lanes of a row at once (a reduce-scatter): lane li
+// returns the row's sum of v[row16_sum4_index(li)].  Neighbours, then pairs,
+// exchange half of what they hold; the four quads are then added by
+// rotations of 4 and 8 lanes, which keep li mod 4.  Lanes that return the
+// same index may differ in the last bits (the additions are associated
+// differently); callers take each sum from a fixed lane.
+__device__ inline int row16_sum4_index(int li) { return 2 * (li & 1) + ((li >> 1) & 1); }
+__device__ inline double row16_sum4(const double (&v)[4], int li) {
+  const bool odd = (li & 1) != 0;
+  double k0 = odd ? v[2] : v[0], k1 = odd ? v[3] : v[1];
+  const double s0 = odd ? v[0] : v[2], s1 = odd ? v[1] : v[3];
+  k0 += dpp_f64<0xB1>(s0);   // quad_perm [1,0,3,2]
+  k1 += dpp_f64<0xB1>(s1);
+  const bool hi = (li & 2) != 0;
+  double k = hi ? k1 : k0;
+  const double s = hi ? k0 : k1;
+  k += dpp_f64<0x4E>(s);     // quad_perm [2,3,0,1]
+  k += dpp_f64<0x124>(k);    // row_ror:4
+  k += dpp_f64<0x128>(k);    // row_ror:8
+  return k;
+}
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 

@@ -1397,6 +1397,16 @@ __device__ inline void widen_tile_row(C (&v)[4]) {
   }
 }
 
+// Four FP32 values rounded to BF16 (to nearest, ties to even) by the packed
+// conversion instruction, as two words of two elements each (element 0 in the
+// low half of a).
+__device__ inline void bf16_pack4(const float (&v)[4], uint32_t& a, uint32_t& b) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 h2 __attribute__((ext_vector_type(2)));
+  a = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2{v[0], v[1]}), h2));
+  b = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2{v[2], v[3]}), h2));
+}
+
 template <typename T, typename C>
 __device__ inline void store_tile_row(T* rowp, int K, int lk, int cols, bool ok, bool vec, const C (&v)[4]) {
   if (!ok) return;
@@ -1683,7 +1693,6 @@ __global__ __launch_bounds__(64 * W) void trsm_wide_kernel(int64_t rows, T* Y, i
                                                            double* colpart) {
   using C = float;
   using V = v4f;
-  constexpr int NS = (MT + 15) / 16;
   constexpr int H = MT / 2;   // ring slots
   constexpr int L = 16 * MT;
   extern __shared__ __align__(16) unsigned char trsm_smem[];
@@ -1703,11 +1712,12 @@ __global__ __launch_bounds__(64 * W) void trsm_wide_kernel(int64_t rows, T* Y, i
     }
     __syncthreads();
   }
-  double cacc[NS][4];
+  // column sums: lane li keeps column 4 lk + row16_sum4_index(li) of the tiles
+  // K with K mod 4 = li / 4
+  constexpr int NS4 = (MT + 3) / 4;
+  double cacc[NS4];
 #pragma unroll
-  for (int s2 = 0; s2 < NS; ++s2)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) cacc[s2][r] = 0.0;
+  for (int s2 = 0; s2 < NS4; ++s2) cacc[s2] = 0.0;
   const int64_t ntiles = (rows + 15) / 16;
   const int64_t tstride = static_cast<int64_t>(gridDim.x) * W;
   int64_t rt = static_cast<int64_t>(blockIdx.x) * W + wave;
@@ -1777,18 +1787,26 @@ __global__ __launch_bounds__(64 * W) void trsm_wide_kernel(int64_t rows, T* Y, i
       out += out2;
 #pragma unroll
       for (int r = 0; r < 4; ++r) q[K][r] = out[r];
-      store_tile_row<T, C>(rowp, K, lk, L, rok, true, q[K]);
+      // the stored values (BF16: rounded once, for the store and the sums)
+      double cs[4];
+      if constexpr (std::is_same<T, bf16>::value) {
+        uint32_t wa, wb;
+        bf16_pack4(q[K], wa, wb);
+        if (rok) *reinterpret_cast<uint2*>(rowp + 16 * K + 4 * lk) = make_uint2(wa, wb);
+        cs[0] = __uint_as_float(wa << 16);
+        cs[1] = __uint_as_float(wa & 0xffff0000u);
+        cs[2] = __uint_as_float(wb << 16);
+        cs[3] = __uint_as_float(wb & 0xffff0000u);
+      } else {
+        store_tile_row<T, C>(rowp, K, lk, L, rok, true, q[K]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cs[r] = q[K][r];
+      }
       if (colpart) {
-        double cs[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          cs[r] = rok ? static_cast<double>(stored_as<T, C>(q[K][r])) : 0.0;
-          cs[r] = row16_sum(cs[r]);   // DPP: no LDS traffic
-        }
-        if (li == (K & 15)) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) cacc[K >> 4][r] += cs[r];
-        }
+        for (int r = 0; r < 4; ++r) cs[r] = rok ? cs[r] : 0.0;
+        const double s = row16_sum4(cs, li);   // DPP: no LDS traffic
+        if ((li >> 2) == (K & 3)) cacc[K >> 2] += s;
       }
     }
   }
@@ -1796,12 +1814,9 @@ __global__ __launch_bounds__(64 * W) void trsm_wide_kernel(int64_t rows, T* Y, i
     __syncthreads();   // every wave is done with the factor: its LDS takes the sums
     double* csw = reinterpret_cast<double*>(trsm_smem);
 #pragma unroll
-    for (int s2 = 0; s2 < NS; ++s2) {
-      const int K = li + 16 * s2;
-      if (K < MT) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) csw[wave * L + 16 * K + drow<C>(lk, r)] = cacc[s2][r];
-      }
+    for (int s2 = 0; s2 < NS4; ++s2) {
+      const int K = 4 * s2 + (li >> 2);
+      if (K < MT) csw[wave * L + 16 * K + drow<C>(lk, row16_sum4_index(li))] = cacc[s2];
     }
     __syncthreads();
     for (int col = threadIdx.x; col < L; col += blockDim.x) {

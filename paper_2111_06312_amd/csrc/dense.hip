@@ -1397,14 +1397,11 @@ __device__ inline void widen_tile_row(C (&v)[4]) {
   }
 }
 
-// Four FP32 values rounded to BF16 (to nearest, ties to even) by the packed
-// conversion instruction, as two words of two elements each (element 0 in the
-// low half of a).
+// Four FP32 values rounded to BF16 (to nearest, ties to even), as two words
+// of two elements each (element 0 in the low half of a).
 __device__ inline void bf16_pack4(const float (&v)[4], uint32_t& a, uint32_t& b) {
-  typedef float f2 __attribute__((ext_vector_type(2)));
-  typedef __bf16 h2 __attribute__((ext_vector_type(2)));
-  a = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2{v[0], v[1]}), h2));
-  b = __builtin_bit_cast(uint32_t, __builtin_convertvector((f2{v[2], v[3]}), h2));
+  a = float2_to_bf16x2(v[0], v[1]);
+  b = float2_to_bf16x2(v[2], v[3]);
 }
 
 template <typename T, typename C>
@@ -1416,8 +1413,8 @@ __device__ inline void store_tile_row(T* rowp, int K, int lk, int cols, bool ok,
       if constexpr (std::is_same<T, float>::value) {
         *reinterpret_cast<float4*>(rowp + c0) = make_float4(v[0], v[1], v[2], v[3]);
       } else {
-        const uint32_t a = static_cast<uint32_t>(float_to_bf16(v[0])) | (static_cast<uint32_t>(float_to_bf16(v[1])) << 16);
-        const uint32_t b = static_cast<uint32_t>(float_to_bf16(v[2])) | (static_cast<uint32_t>(float_to_bf16(v[3])) << 16);
+        uint32_t a, b;
+        bf16_pack4(v, a, b);
         *reinterpret_cast<uint2*>(rowp + c0) = make_uint2(a, b);
       }
       return;

@@ -109,9 +109,7 @@ template <> struct Chunk<bf16, float, true> {
     if (valid >= N) {
       uint32_t w[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        w[t] = static_cast<uint32_t>(float_to_bf16(x[2 * t])) |
-               (static_cast<uint32_t>(float_to_bf16(x[2 * t + 1])) << 16);
+      for (int t = 0; t < 4; ++t) w[t] = float2_to_bf16x2(x[2 * t], x[2 * t + 1]);
       stream_store(v4u_stream{w[0], w[1], w[2], w[3]}, reinterpret_cast<v4u_stream*>(p));
     } else {
       for (int t = 0; t < valid; ++t) p[t].bits = float_to_bf16(x[t]);

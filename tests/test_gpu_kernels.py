@@ -35,6 +35,25 @@ def test_device_gaussian_matches_oracle_philox(gpu_lib):
     assert np.array_equal(a, b)
 
 
+def test_device_bf16_rounding_is_round_to_nearest_even(gpu_lib):
+    # BF16 blocks round on the device with the conversion instruction: the
+    # device's own FP64 draws, rounded to FP32 and then to BF16 by torch on the
+    # CPU (round to nearest, ties to even), must give the same bits.  (The
+    # oracle's draws agree with the device's to 1e-12 only, which can move a
+    # value across an FP32 rounding boundary.)
+    _print_case("bf16 rounding")
+    rows, cols, seed = 4099, 37, 11
+    z = gpu_lib.gaussian_block(rows, cols, seed, torch.bfloat16).cpu()
+    f32 = gpu_lib.gaussian_block(rows, cols, seed, torch.float64).cpu().float()
+    # the block holds exact ties (low 16 bits 0x8000), which must go to the even neighbour
+    assert int(((f32.view(torch.int32) & 0xffff) == 0x8000).sum()) >= 3
+    want = f32.to(torch.bfloat16)
+    assert torch.equal(z.view(torch.int16), want.view(torch.int16))
+    # the reference's own tie rule
+    x = torch.tensor([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8)], dtype=torch.float32)
+    assert torch.equal(x.to(torch.bfloat16).float(), torch.tensor([1.0, 1.0 + 4 * 2.0 ** -8, -1.0]))
+
+
 # ---------------------------------------------------------------- Gram
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])

@@ -50,20 +50,19 @@ __host__ __device__ inline float bf16_to_float(uint16_t b) {
   return v.f;
 }
 
-// Round to nearest, ties to even.  NaN stays NaN (quiet).  (The packed
-// conversion instruction of gfx950 was measured to round ties to the odd
-// neighbour, so the rounding is done on the bits.)
-__host__ __device__ inline uint16_t float_to_bf16(float f) {
+// Round to nearest, ties to even, on the bits and without branches; NaN
+// stays NaN (quiet).  (The packed conversion instruction of gfx950 was
+// measured to round ties to the odd neighbour.)
+__host__ __device__ inline uint32_t bf16_round_high(float f) {
   union { uint32_t u; float f; } v;
   v.f = f;
-  uint32_t u = v.u;
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return static_cast<uint16_t>((u >> 16) | 0x40u);
-  uint32_t lsb = (u >> 16) & 1u;
-  u += 0x7fffu + lsb;
-  return static_cast<uint16_t>(u >> 16);
+  const uint32_t u = v.u;
+  const uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+  return (u & 0x7fffffffu) > 0x7f800000u ? (u | 0x400000u) : r;   // the result in bits 31..16
 }
+__host__ __device__ inline uint16_t float_to_bf16(float f) { return static_cast<uint16_t>(bf16_round_high(f) >> 16); }
 __host__ __device__ inline uint32_t float2_to_bf16x2(float lo, float hi) {
-  return static_cast<uint32_t>(float_to_bf16(lo)) | (static_cast<uint32_t>(float_to_bf16(hi)) << 16);
+  return (bf16_round_high(lo) >> 16) | (bf16_round_high(hi) & 0xffff0000u);
 }
 
 // Element conversions between storage types and compute types.
